@@ -1,0 +1,174 @@
+/*
+ * rlx.h -- RANLUX++ random numbers on an AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of librlx.so.  The generator is RANLUX++ as described by Hahnfeld &
+ * Moneta, "A Portable Implementation of RANLUX++" (arXiv 2106.02504):
+ *
+ *   - the state of a stream is the LCG state X in [0, m) with
+ *     m = 2^576 - 2^240 + 1 (section 2.2), stored as nine 64-bit words
+ *     (section 2), plus the position of the next 48-bit field (section 2);
+ *   - one generator step is X <- A_p X mod m, A_p = a^p mod m, where a is the
+ *     LCG multiplier equivalent to one subtract-with-borrow step of RANLUX
+ *     and p the luxury level (section 1; the multiply and the reduction are
+ *     sections 2.1 and 2.2);
+ *   - the numbers of a step are obtained by converting X back to the 24
+ *     RANLUX numbers (section 2.3) and taking 48 bits per value, 12 values
+ *     per step (section 2.3);
+ *   - seeding and skipping use exponentiation by squaring (section 2.4).
+ *
+ * Conventions shared by every entry point:
+ *
+ *   Memory     All array pointers are DEVICE pointers owned by the caller
+ *              (e.g. PyTorch tensors).  The library never allocates, frees or
+ *              retains caller memory.  It owns only per-(device, p) constant
+ *              tables and one error word per device.
+ *   Streams    `stream` is a hipStream_t passed as void*; NULL is the default
+ *              stream.  Work runs on the current HIP device and is enqueued
+ *              asynchronously: calls return before the GPU has finished, and
+ *              faults surface at the caller's next synchronisation.  The first
+ *              call with a new luxury level p on a device builds that level's
+ *              tables on `stream` and waits for them (about a millisecond);
+ *              call rlx_prepare() first when the caller must not block, e.g.
+ *              before capturing a HIP graph.
+ *   Errors     Functions return RLX_OK (0) or a positive error code; the
+ *              library never aborts and never prints.  rlx_strerror() gives a
+ *              message.  Invalid stream records found by a kernel (x >= m,
+ *              pos > 11, or a luxury level different from `p`) are skipped --
+ *              their outputs are left unwritten -- and flagged in the device
+ *              error word, which rlx_check_errors() reads and clears.
+ *   Sizes      n = 0 or count = 0 is a no-op returning RLX_OK.
+ *   Threads    Entry points may be called from several host threads.
+ *   Overlap    Output arrays must not overlap the state array or each other.
+ */
+#ifndef RLX_H
+#define RLX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Stream record, 80 bytes, 16-byte aligned in arrays.
+ *   x[9]  LCG state X, little-endian 64-bit words (x[0] least significant);
+ *         must satisfy X < m.
+ *   pos   number of 48-bit fields of the current step already used, 0..11.
+ *         Records are kept in canonical form: the step is advanced as soon
+ *         as its 12th field is used, so (x, pos) is a unique function of the
+ *         number of values drawn since seeding.
+ *   p     luxury level the record belongs to (>= 24). */
+typedef struct rlx_state {
+    uint64_t x[9];
+    uint32_t pos;
+    uint32_t p;
+} rlx_state;
+
+enum {
+    RLX_OK = 0,
+    RLX_EINVAL = 1,   /* bad argument: NULL with n > 0, p < 24, misalignment, overflow */
+    RLX_EHIP = 2,     /* HIP runtime or launch error */
+    RLX_ENOMEM = 3,   /* table allocation failed */
+    RLX_ESTATE = 4    /* a kernel found an invalid stream record */
+};
+
+/* Error-word bits reported by rlx_check_errors(). */
+#define RLX_ERR_BAD_P    0x1u   /* record's p differs from the call's p */
+#define RLX_ERR_BAD_POS  0x2u   /* record's pos > 11 */
+#define RLX_ERR_BAD_X    0x4u   /* record's X >= m */
+
+/* Message for an error code (static string). */
+const char *rlx_strerror(int code);
+
+/* Library version, e.g. "rlx 0.1 gfx950". */
+const char *rlx_version(void);
+
+/* Build (if needed) the constant tables of luxury level p on the current
+ * device, on `stream`, and wait for them.  p >= 24.  Tables: A_p folded for
+ * the generator step, and A_p^(j 16^i) for i < 40, j < 16 used by seeding and
+ * skipping (section 2.4: exponentiation by squaring, here with 4-bit
+ * windows). */
+int rlx_prepare(uint32_t p, void *stream);
+
+/* Seeding (section 2.4).  states[i] <- stream record of seed id
+ * ids[i] (or id0 + i when ids == NULL) at luxury level p:
+ *   x = A_p^(2^96 id) mod m applied to X = 1, pos = 0, p = p.
+ * Seed ids are therefore 2^96 generator steps apart.  ids: device array of n
+ * uint64 or NULL; id0 + n - 1 must not overflow 64 bits. */
+int rlx_init_streams(rlx_state *states, uint64_t n, const uint64_t *ids,
+                     uint64_t id0, uint32_t p, void *stream);
+
+/* Skip-ahead (section 2.4).  For every record i with luxury level p:
+ *   x <- A_p^k x mod m, pos unchanged,
+ * with k = steps[i] (or steps0 when steps == NULL) GENERATOR STEPS; one step
+ * is 12 values, so this advances the stream by 12 k values.  k < 2^64. */
+int rlx_skip(rlx_state *states, uint64_t n, const uint64_t *steps,
+             uint64_t steps0, uint32_t p, void *stream);
+
+/* Uniform doubles (section 2.3).  For every record i (luxury level p), draw
+ * `count` values into out[i * count + j], j < count, and advance the record.
+ * A value is a 48-bit field v of the step's RANLUX numbers, converted as
+ * v * 2^-48 (exact; in [0, 1), 0 possible).  Field k of a step is bits
+ * [48k, 48k + 48) of D = floor(X 2^576 / m), the 24 RANLUX numbers packed
+ * with the oldest number in the least significant 24 bits.  out must be
+ * 8-byte aligned; n * count must not overflow. */
+int rlx_generate_f64(rlx_state *states, uint64_t n, uint64_t count,
+                     double *out, uint32_t p, void *stream);
+
+/* The same draws as rlx_generate_f64, as the 48-bit integers v,
+ * zero-extended to 64 bits (section 2.4's integer draw). */
+int rlx_generate_u64(rlx_state *states, uint64_t n, uint64_t count,
+                     uint64_t *out, uint32_t p, void *stream);
+
+/* rlx_generate_f64 that also writes the LCG state of every step it visits:
+ * trace[(i * steps_per_stream + t) * 9 + w], t = 0 is the state on entry and
+ * t = 1..A the states after each of the A = (pos + count) / 12 advances, so
+ * steps_per_stream must be >= A + 1 for every record (all records must then
+ * share one pos).  Returns RLX_EINVAL if steps_per_stream is too small for
+ * pos = 11. */
+int rlx_generate_f64_trace(rlx_state *states, uint64_t n, uint64_t count,
+                           double *out, uint64_t *trace,
+                           uint64_t steps_per_stream, uint32_t p, void *stream);
+
+/* Synchronise `stream`, then read and clear the device error word of the
+ * current device: *flags receives the RLX_ERR_* bits set by kernels since
+ * the last call.  Returns RLX_ESTATE if any bit was set. */
+int rlx_check_errors(void *stream, uint32_t *flags);
+
+/* ---- host-only introspection (no GPU needed) ---------------------------- */
+
+/* The modulus m and the multiplier a (one SWB step) as eighteen 32-bit
+ * words, least significant first. */
+void rlx_constants(uint32_t m_words[18], uint32_t a_words[18]);
+
+/* ---- test-only entry points ----------------------------------------------
+ * These run the library's generic 576-bit arithmetic on arbitrary operands so
+ * that tests can reach rare branches.  Arrays are device arrays of n records
+ * of nine uint64 words. */
+
+/* out[i] = x[i] * y[i] mod m (sections 2.1, 2.2): the full 1152-bit product
+ * reduced to the canonical residue.  x[i], y[i] < 2^576 (need not be < m). */
+int rlx_test_mulmod(const uint64_t *x, const uint64_t *y, uint64_t *out,
+                    uint64_t n, void *stream);
+
+/* out[i] = base[i]^e mod m with e = exps[3 i] + 2^64 exps[3 i + 1] +
+ * 2^128 exps[3 i + 2] (square and multiply). base[i] < 2^576. */
+int rlx_test_pow(const uint64_t *base, const uint64_t *exps, uint64_t *out,
+                 uint64_t n, void *stream);
+
+/* The conversion of section 2.3 on canonical X (< m): d[i] = the 24 RANLUX
+ * numbers packed as D = floor(X 2^576 / m) (nine words), carry[i] = the
+ * RANLUX carry bit c = X - D + floor(D / 2^336). */
+int rlx_test_to_ranlux(const uint64_t *x, uint64_t *d, uint32_t *carry,
+                       uint64_t n, void *stream);
+
+/* rlx_generate_u64 with every rare-case branch of the step and the
+ * conversion taken by all lanes (the exact general code), so that the general
+ * code can be compared with the fast path on ordinary inputs. */
+int rlx_test_generate_u64_general(rlx_state *states, uint64_t n, uint64_t count,
+                                  uint64_t *out, uint32_t p, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RLX_H */

@@ -1,0 +1,232 @@
+"""rlx -- RANLUX++ random numbers on an AMD MI355X (gfx950).
+
+Thin ctypes binding over librlx.so (see include/rlx.h).  Every step of the
+generator runs in the library's HIP kernels; this module only marshals
+PyTorch tensors (device memory) and the current HIP stream into the C ABI.
+There is no CPU implementation here: if the library is missing, every call
+raises.
+
+Stream records are ``int64`` tensors of shape ``[n, 10]`` on a CUDA (HIP)
+device: words 0..8 hold the 576-bit LCG state X (least significant first),
+word 9 holds ``pos | p << 32``.
+
+Paper: Hahnfeld & Moneta, "A Portable Implementation of RANLUX++",
+arXiv 2106.02504.  Seeding/skipping: section 2.4; generation: sections
+2.1-2.3.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # load torch's HIP runtime first: librlx.so binds to the same one
+
+__all__ = [
+    "RlxError", "lib", "new_states", "prepare", "init_streams", "skip",
+    "generate_f64", "generate_u64", "generate_f64_trace", "check_errors",
+    "constants", "test_mulmod", "test_pow", "test_to_ranlux",
+    "test_generate_u64_general", "STATE_WORDS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librlx.so")
+STATE_WORDS = 10
+
+_u64 = ctypes.c_uint64
+_u32 = ctypes.c_uint32
+_vp = ctypes.c_void_p
+_int = ctypes.c_int
+
+_SIGS = {
+    "rlx_strerror": (ctypes.c_char_p, [_int]),
+    "rlx_version": (ctypes.c_char_p, []),
+    "rlx_prepare": (_int, [_u32, _vp]),
+    "rlx_init_streams": (_int, [_vp, _u64, _vp, _u64, _u32, _vp]),
+    "rlx_skip": (_int, [_vp, _u64, _vp, _u64, _u32, _vp]),
+    "rlx_generate_f64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
+    "rlx_generate_u64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
+    "rlx_generate_f64_trace": (_int, [_vp, _u64, _u64, _vp, _vp, _u64, _u32, _vp]),
+    "rlx_check_errors": (_int, [_vp, ctypes.POINTER(_u32)]),
+    "rlx_constants": (None, [ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
+    "rlx_test_mulmod": (_int, [_vp, _vp, _vp, _u64, _vp]),
+    "rlx_test_pow": (_int, [_vp, _vp, _vp, _u64, _vp]),
+    "rlx_test_to_ranlux": (_int, [_vp, _vp, _vp, _u64, _vp]),
+    "rlx_test_generate_u64_general": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
+}
+
+_lib = None
+
+
+class RlxError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = lib().rlx_strerror(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} (code {code})")
+        self.code = code
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded librlx.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2106_02504_amd.build`")
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(code: int, where: str) -> None:
+    if code != 0:
+        raise RlxError(code, where)
+
+
+def _stream(device: torch.device | None = None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: torch.Tensor | None) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _need_states(states: torch.Tensor) -> int:
+    if states.dtype != torch.int64 or states.dim() != 2 or states.shape[1] != STATE_WORDS:
+        raise ValueError("states must be an int64 tensor of shape [n, 10]")
+    if not states.is_cuda or not states.is_contiguous():
+        raise ValueError("states must be a contiguous device tensor")
+    return states.shape[0]
+
+
+def _need_u64_vector(t: torch.Tensor, n: int, what: str) -> None:
+    if t.dtype not in (torch.int64, torch.uint64) or t.numel() != n or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{what} must be a contiguous device int64/uint64 tensor with {n} elements")
+
+
+def new_states(n: int, device: str | torch.device = "cuda") -> torch.Tensor:
+    """Uninitialised-but-zeroed record array; fill it with init_streams()."""
+    return torch.zeros((n, STATE_WORDS), dtype=torch.int64, device=device)
+
+
+def prepare(p: int) -> None:
+    """Build the tables of luxury level p on the current device now."""
+    _check(lib().rlx_prepare(p, _stream()), "rlx_prepare")
+
+
+def init_streams(states: torch.Tensor, p: int, ids: torch.Tensor | None = None, id0: int = 0) -> torch.Tensor:
+    """states[i] <- seed(ids[i] or id0 + i, p) (section 2.4)."""
+    n = _need_states(states)
+    if ids is not None:
+        _need_u64_vector(ids, n, "ids")
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_init_streams(states.data_ptr(), n, _ptr(ids), id0, p, _stream()), "rlx_init_streams")
+    return states
+
+
+def skip(states: torch.Tensor, steps, p: int) -> torch.Tensor:
+    """Advance every record by `steps` generator steps (12 values each):
+    an int for all, or a device tensor of n uint64/int64 (section 2.4)."""
+    n = _need_states(states)
+    if isinstance(steps, torch.Tensor):
+        _need_u64_vector(steps, n, "steps")
+        ptr, s0 = steps.data_ptr(), 0
+    else:
+        ptr, s0 = None, int(steps)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_skip(states.data_ptr(), n, ptr, s0, p, _stream()), "rlx_skip")
+    return states
+
+
+def _out(states: torch.Tensor, count: int, dtype: torch.dtype, out: torch.Tensor | None) -> torch.Tensor:
+    n = states.shape[0]
+    if out is None:
+        return torch.empty((n, count), dtype=dtype, device=states.device)
+    if out.dtype != dtype or out.numel() != n * count or not out.is_contiguous() or out.device != states.device:
+        raise ValueError(f"out must be a contiguous {dtype} tensor with n*count elements on the states' device")
+    return out
+
+
+def generate_f64(states: torch.Tensor, count: int, p: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """`count` uniform doubles per record, shape [n, count] (section 2.3)."""
+    n = _need_states(states)
+    out = _out(states, count, torch.float64, out)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_generate_f64(states.data_ptr(), n, count, out.data_ptr(), p, _stream()), "rlx_generate_f64")
+    return out
+
+
+def generate_u64(states: torch.Tensor, count: int, p: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """The same draws as 48-bit integers (int64 tensor, values < 2^48)."""
+    n = _need_states(states)
+    out = _out(states, count, torch.int64, out)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_generate_u64(states.data_ptr(), n, count, out.data_ptr(), p, _stream()), "rlx_generate_u64")
+    return out
+
+
+def generate_f64_trace(states: torch.Tensor, count: int, p: int):
+    """generate_f64 plus the LCG state of every step visited:
+    returns (values [n, count], trace [n, steps, 9] int64)."""
+    n = _need_states(states)
+    steps = (11 + count) // 12 + 1
+    out = _out(states, count, torch.float64, None)
+    trace = torch.zeros((n, steps, 9), dtype=torch.int64, device=states.device)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_generate_f64_trace(states.data_ptr(), n, count, out.data_ptr(), trace.data_ptr(),
+                                            steps, p, _stream()), "rlx_generate_f64_trace")
+    return out, trace
+
+
+def check_errors() -> int:
+    """Synchronise and return (and clear) the device error bits."""
+    flags = _u32(0)
+    code = lib().rlx_check_errors(_stream(), ctypes.byref(flags))
+    if code not in (0, 4):
+        _check(code, "rlx_check_errors")
+    return flags.value
+
+
+def constants() -> tuple[int, int]:
+    """(m, a) as the library holds them (host-only call)."""
+    m = (_u32 * 18)()
+    a = (_u32 * 18)()
+    lib().rlx_constants(m, a)
+    return (sum(int(w) << (32 * k) for k, w in enumerate(m)),
+            sum(int(w) << (32 * k) for k, w in enumerate(a)))
+
+
+# ---- test-only entry points ------------------------------------------------
+
+def test_mulmod(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    n = x.shape[0]
+    out = torch.empty_like(x)
+    _check(lib().rlx_test_mulmod(x.data_ptr(), y.data_ptr(), out.data_ptr(), n, _stream()), "rlx_test_mulmod")
+    return out
+
+
+def test_pow(base: torch.Tensor, exps: torch.Tensor) -> torch.Tensor:
+    n = base.shape[0]
+    out = torch.empty_like(base)
+    _check(lib().rlx_test_pow(base.data_ptr(), exps.data_ptr(), out.data_ptr(), n, _stream()), "rlx_test_pow")
+    return out
+
+
+def test_to_ranlux(x: torch.Tensor):
+    n = x.shape[0]
+    d = torch.empty_like(x)
+    carry = torch.empty((n,), dtype=torch.int32, device=x.device)
+    _check(lib().rlx_test_to_ranlux(x.data_ptr(), d.data_ptr(), carry.data_ptr(), n, _stream()),
+           "rlx_test_to_ranlux")
+    return d, carry
+
+
+def test_generate_u64_general(states: torch.Tensor, count: int, p: int) -> torch.Tensor:
+    n = _need_states(states)
+    out = _out(states, count, torch.int64, None)
+    _check(lib().rlx_test_generate_u64_general(states.data_ptr(), n, count, out.data_ptr(), p, _stream()),
+           "rlx_test_generate_u64_general")
+    return out

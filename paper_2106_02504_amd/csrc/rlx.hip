@@ -1,0 +1,609 @@
+// rlx.hip -- RANLUX++ kernels for gfx950 and the C ABI of librlx.so.
+//
+// Kernels (one lane per stream record unless noted):
+//   k_tab_base / k_tab_fill / k_tab_fold   per-luxury-level constant tables
+//   k_init                                 seeding        (section 2.4)
+//   k_skip                                 skip-ahead     (section 2.4)
+//   k_generate<F64|U64, trace>             draw values    (sections 2.1-2.3)
+//   k_test_*                               generic arithmetic for tests
+//
+// Tables of a luxury level p (device memory owned by the library):
+//   T[i][j] = A_p^(j 16^i) mod m, i < 40, j < 16 (18 words each): 4-bit
+//             windows of a 160-bit exponent; rows 0..15 serve skips of k <
+//             2^64 steps, rows 24..39 serve seeds (exponent 2^96 id).
+//   C[j]    = A_p 2^(27 j) mod m, j < 22: the folded multiplier of the
+//             generator step (see rlx_arith.hpp).
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "rlx.h"
+#include "rlx_arith.hpp"
+
+using namespace rlx;
+
+namespace {
+
+constexpr int TAB_ROWS = 40;
+constexpr int TAB_COLS = 16;
+constexpr int SEED_ROW0 = 24;  // 2^96 = 16^24
+constexpr size_t TAB_WORDS = (size_t)TAB_ROWS * TAB_COLS * NW;
+constexpr size_t FOLD_WORDS = (size_t)NL * NW;
+constexpr int BLOCK = 256;
+
+// a = 2^576 - 2^552 - 2^240 + 2^216 + 1 = 2^-24 mod m: one subtract-with-
+// borrow step of RANLUX (lags 24 and 10, base 2^24) as an LCG multiplier.
+__device__ __forceinline__ uint32_t a_word(int k) {
+  return k == 0 ? 1u
+       : k < 6  ? 0u
+       : k == 6 ? 0x01000000u
+       : k == 7 ? 0xFFFF0000u
+       : k < 17 ? 0xFFFFFFFFu
+                : 0xFFFFFEFFu;
+}
+
+__device__ __forceinline__ void set_one(uint32_t (&x)[NW]) {
+#pragma unroll
+  for (int k = 0; k < NW; ++k) x[k] = k == 0 ? 1u : 0u;
+}
+
+__device__ __forceinline__ void load_words(const uint32_t* __restrict__ src, uint32_t (&x)[NW]) {
+#pragma unroll
+  for (int k = 0; k < NW; ++k) x[k] = src[k];
+}
+
+__device__ __forceinline__ void store_words(uint32_t* __restrict__ dst, const uint32_t (&x)[NW]) {
+#pragma unroll
+  for (int k = 0; k < NW; ++k) dst[k] = x[k];
+}
+
+__device__ __forceinline__ void copy_words(uint32_t (&dst)[NW], const uint32_t (&src)[NW]) {
+#pragma unroll
+  for (int k = 0; k < NW; ++k) dst[k] = src[k];
+}
+
+// record i: 80 bytes = five 16-byte vectors
+__device__ __forceinline__ void load_record(const rlx_state* __restrict__ st, uint64_t i,
+                                            uint32_t (&x)[NW], uint32_t& pos, uint32_t& p) {
+  const uint4* r = reinterpret_cast<const uint4*>(st + i);
+  uint4 v[5];
+#pragma unroll
+  for (int q = 0; q < 5; ++q) v[q] = r[q];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    x[4 * q + 0] = v[q].x; x[4 * q + 1] = v[q].y; x[4 * q + 2] = v[q].z; x[4 * q + 3] = v[q].w;
+  }
+  x[16] = v[4].x; x[17] = v[4].y;
+  pos = v[4].z;
+  p = v[4].w;
+}
+
+__device__ __forceinline__ void store_record(rlx_state* __restrict__ st, uint64_t i,
+                                             const uint32_t (&x)[NW], uint32_t pos, uint32_t p) {
+  uint4* r = reinterpret_cast<uint4*>(st + i);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) r[q] = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+  r[4] = make_uint4(x[16], x[17], pos, p);
+}
+
+__device__ __forceinline__ uint32_t check_record(const uint32_t (&x)[NW], uint32_t pos, uint32_t sp,
+                                                 uint32_t p) {
+  uint32_t bad = 0;
+  if (sp != p) bad |= RLX_ERR_BAD_P;
+  if (pos > 11) bad |= RLX_ERR_BAD_POS;
+  if (geq_m(x)) bad |= RLX_ERR_BAD_X;
+  return bad;
+}
+
+// Row-offset barrier for the generator step: an empty asm that claims to
+// modify the (scalar) offset, so the table loads using it stay in place.
+struct SgprBarrier {
+  __device__ __forceinline__ uint32_t operator()(uint32_t v) const {
+    asm volatile("" : "+s"(v));
+    return v;
+  }
+};
+
+__device__ __forceinline__ void mulmod_inplace(uint32_t (&x)[NW], const uint32_t (&y)[NW]) {
+  uint32_t r[NW];
+  mulmod_generic(x, y, r);
+  copy_words(x, r);
+}
+
+// ---------------------------------------------------------------------------
+// tables
+
+// One lane: A_p = a^p by square-and-multiply, then T[i][1] = T[i-1][1]^16,
+// and T[i][0] = 1.
+__global__ __launch_bounds__(64) void k_tab_base(uint32_t* __restrict__ T, uint32_t p) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  uint32_t a[NW], r[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) a[k] = a_word(k);
+  set_one(r);
+  const int top = 31 - __builtin_clz(p);
+  for (int b = top; b >= 0; --b) {
+    mulmod_inplace(r, r);
+    if ((p >> b) & 1u) mulmod_inplace(r, a);
+  }
+  uint32_t one[NW];
+  set_one(one);
+  for (int i = 0; i < TAB_ROWS; ++i) {
+    store_words(T + ((size_t)i * TAB_COLS + 0) * NW, one);
+    store_words(T + ((size_t)i * TAB_COLS + 1) * NW, r);
+    for (int s = 0; s < 4; ++s) mulmod_inplace(r, r);
+  }
+}
+
+// T[i][j] = T[i][1]^j for 2 <= j < 16, one lane per entry.
+__global__ __launch_bounds__(64) void k_tab_fill(uint32_t* __restrict__ T) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= TAB_ROWS * (TAB_COLS - 2)) return;
+  const int i = t / (TAB_COLS - 2);
+  const uint32_t j = 2 + t % (TAB_COLS - 2);
+  uint32_t base[NW], r[NW];
+  load_words(T + ((size_t)i * TAB_COLS + 1) * NW, base);
+  copy_words(r, base);
+  const int top = 31 - __builtin_clz(j);
+  for (int b = top - 1; b >= 0; --b) {
+    mulmod_inplace(r, r);
+    if ((j >> b) & 1u) mulmod_inplace(r, base);
+  }
+  store_words(T + ((size_t)i * TAB_COLS + j) * NW, r);
+}
+
+// C[j] = A_p 2^(27 j) mod m, one lane per row.
+__global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T, uint32_t* __restrict__ C) {
+  const int j = threadIdx.x;
+  if (j >= NL) return;
+  uint32_t a[NW], pw[NW], r[NW];
+  load_words(T + (size_t)1 * NW, a);  // T[0][1] = A_p
+  const int bit = LB * j;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) pw[k] = (k == (bit >> 5)) ? (1u << (bit & 31)) : 0u;
+  mulmod_generic(a, pw, r);
+  store_words(C + (size_t)j * NW, r);
+}
+
+// ---------------------------------------------------------------------------
+// seeding and skipping (section 2.4)
+
+__global__ __launch_bounds__(BLOCK) void k_init(rlx_state* __restrict__ st, uint64_t n,
+                                                const uint64_t* __restrict__ ids, uint64_t id0,
+                                                uint32_t p, const uint32_t* __restrict__ T) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const uint64_t id = ids ? ids[i] : id0 + i;
+  uint32_t x[NW];
+  set_one(x);
+  bool first = true;
+  for (int nib = 0; nib < 16 && (id >> (4 * nib)) != 0; ++nib) {
+    const uint32_t v = (uint32_t)(id >> (4 * nib)) & 15u;
+    if (v == 0) continue;
+    const uint32_t* e = T + ((size_t)(SEED_ROW0 + nib) * TAB_COLS + v) * NW;
+    uint32_t y[NW];
+    load_words(e, y);
+    if (first) {
+      copy_words(x, y);
+      first = false;
+    } else {
+      mulmod_inplace(x, y);
+    }
+  }
+  store_record(st, i, x, 0u, p);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint64_t n,
+                                                const uint64_t* __restrict__ steps, uint64_t steps0,
+                                                uint32_t p, const uint32_t* __restrict__ T,
+                                                uint32_t* __restrict__ err) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t x[NW], pos, sp;
+  load_record(st, i, x, pos, sp);
+  const uint32_t bad = check_record(x, pos, sp, p);
+  if (bad) {
+    atomicOr(err, bad);
+    return;
+  }
+  const uint64_t k = steps ? steps[i] : steps0;
+  for (int nib = 0; nib < 16 && (k >> (4 * nib)) != 0; ++nib) {
+    const uint32_t v = (uint32_t)(k >> (4 * nib)) & 15u;
+    if (v == 0) continue;
+    uint32_t y[NW];
+    load_words(T + ((size_t)nib * TAB_COLS + v) * NW, y);
+    mulmod_inplace(x, y);
+  }
+  store_record(st, i, x, pos, sp);
+}
+
+// ---------------------------------------------------------------------------
+// generation (sections 2.1-2.3)
+
+template <bool F64>
+__device__ __forceinline__ void put(void* __restrict__ row, uint64_t j, const uint32_t (&d)[NW], int f) {
+  if (F64) {
+    reinterpret_cast<double*>(row)[j] = field_f64(d, f);
+  } else {
+    reinterpret_cast<uint64_t*>(row)[j] = field_u64(d, f);
+  }
+}
+
+__device__ __forceinline__ void put_trace(uint64_t* __restrict__ tr, const uint32_t (&x)[NW]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) tr[k] = ((uint64_t)x[2 * k + 1] << 32) | x[2 * k];
+}
+
+// Draw `count` values for every record.  Block t of a record holds the 12
+// fields of the t-th state visited; the value with output index j is field
+// (pos + j) mod 12 of block (pos + j) / 12.  The record is advanced eagerly
+// (pos ends in 0..11).
+template <bool F64, bool TRACE>
+__global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, uint64_t n,
+                                                    uint64_t count, void* __restrict__ out,
+                                                    uint64_t* __restrict__ trace, uint64_t trace_steps,
+                                                    const uint32_t* __restrict__ ctab, uint32_t p,
+                                                    uint32_t* __restrict__ err, int force_general) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t x[NW], pos, sp;
+  load_record(st, i, x, pos, sp);
+  const uint32_t bad = check_record(x, pos, sp, p);
+  if (bad) {
+    atomicOr(err, bad);
+    return;
+  }
+  const bool force = force_general != 0;
+  const uint64_t total = pos + count;
+  const uint64_t nadv = total / 12;
+  const uint32_t rem = (uint32_t)(total % 12);
+  char* row = reinterpret_cast<char*>(out) + i * count * 8;
+  uint64_t* tr = TRACE ? trace + i * trace_steps * 9 : nullptr;
+  uint32_t d[NW];
+
+  // block 0: fields pos .. min(12, pos + count) - 1
+  if (TRACE) put_trace(tr, x);
+  to_ranlux(x, d, force);
+  {
+    const uint64_t end = total < 12 ? total : 12;
+#pragma unroll
+    for (int f = 0; f < 12; ++f)
+      if ((uint32_t)f >= pos && (uint64_t)f < end) put<F64>(row, (uint64_t)f - pos, d, f);
+  }
+  // full blocks 1 .. nadv - 1
+  uint64_t base = 12 - pos;
+  for (uint64_t t = 1; t < nadv; ++t) {
+    step(x, ctab, force, SgprBarrier());
+    if (TRACE) put_trace(tr + t * 9, x);
+    to_ranlux(x, d, force);
+#pragma unroll
+    for (int f = 0; f < 12; ++f) put<F64>(row, base + f, d, f);
+    base += 12;
+  }
+  // last advance; its block contributes fields 0 .. rem - 1
+  if (nadv >= 1) {
+    step(x, ctab, force, SgprBarrier());
+    if (TRACE) put_trace(tr + nadv * 9, x);
+    if (rem) {
+      to_ranlux(x, d, force);
+#pragma unroll
+      for (int f = 0; f < 12; ++f)
+        if ((uint32_t)f < rem) put<F64>(row, base + f, d, f);
+    }
+  }
+  store_record(st, i, x, rem, sp);
+}
+
+// ---------------------------------------------------------------------------
+// test kernels: generic arithmetic on arbitrary operands
+
+__device__ __forceinline__ void load9(const uint64_t* __restrict__ src, uint32_t (&x)[NW]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const uint64_t v = src[k];
+    x[2 * k] = (uint32_t)v;
+    x[2 * k + 1] = (uint32_t)(v >> 32);
+  }
+}
+
+__device__ __forceinline__ void store9(uint64_t* __restrict__ dst, const uint32_t (&x)[NW]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) dst[k] = ((uint64_t)x[2 * k + 1] << 32) | x[2 * k];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_test_mulmod(const uint64_t* __restrict__ xs, const uint64_t* __restrict__ ys,
+                              uint64_t* __restrict__ out, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t x[NW], y[NW], r[NW];
+  load9(xs + i * 9, x);
+  load9(ys + i * 9, y);
+  mulmod_generic(x, y, r);
+  store9(out + i * 9, r);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_test_pow(const uint64_t* __restrict__ bs, const uint64_t* __restrict__ es,
+                           uint64_t* __restrict__ out, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t b[NW], r[NW];
+  load9(bs + i * 9, b);
+  set_one(r);
+  for (int w = 2; w >= 0; --w) {
+    const uint64_t e = es[i * 3 + w];
+    for (int bit = 63; bit >= 0; --bit) {
+      mulmod_inplace(r, r);
+      if ((e >> bit) & 1u) mulmod_inplace(r, b);
+    }
+  }
+  store9(out + i * 9, r);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_test_to_ranlux(const uint64_t* __restrict__ xs, uint64_t* __restrict__ ds,
+                                 uint32_t* __restrict__ carry, uint64_t n) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t x[NW], d[NW];
+  load9(xs + i * 9, x);
+  if (geq_m(x)) {
+#pragma unroll
+    for (int k = 0; k < NW; ++k) d[k] = 0xFFFFFFFFu;
+    store9(ds + i * 9, d);
+    carry[i] = 0xFFFFFFFFu;
+    return;
+  }
+  to_ranlux(x, d, false);
+  store9(ds + i * 9, d);
+  carry[i] = ranlux_carry(x, d);
+}
+
+}  // namespace
+
+// ===========================================================================
+// host side
+
+namespace {
+
+struct Tables {
+  uint32_t* T = nullptr;  // TAB_WORDS
+  uint32_t* C = nullptr;  // FOLD_WORDS
+};
+
+std::mutex g_mu;
+std::map<std::pair<int, uint32_t>, Tables> g_tables;
+std::map<int, uint32_t*> g_err;
+
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
+
+inline bool valid_p(uint32_t p) { return p >= 24 && p < (1u << 31); }
+
+inline int launch_status() {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? RLX_OK : RLX_EHIP;
+}
+
+inline bool grid_for(uint64_t n, dim3* g) {
+  const uint64_t blocks = (n + BLOCK - 1) / BLOCK;
+  if (blocks > 0x7FFFFFFFull) return false;
+  *g = dim3((unsigned)blocks);
+  return true;
+}
+
+int current_device(int* dev) { return hipGetDevice(dev) == hipSuccess ? RLX_OK : RLX_EHIP; }
+
+// device error word of the current device (created zeroed on first use)
+int error_word(hipStream_t s, uint32_t** out) {
+  int dev;
+  if (current_device(&dev)) return RLX_EHIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto it = g_err.find(dev);
+  if (it != g_err.end()) {
+    *out = it->second;
+    return RLX_OK;
+  }
+  uint32_t* w = nullptr;
+  if (hipMalloc(&w, sizeof(uint32_t)) != hipSuccess) return RLX_ENOMEM;
+  if (hipMemsetAsync(w, 0, sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipFree(w);
+    return RLX_EHIP;
+  }
+  g_err[dev] = w;
+  *out = w;
+  return RLX_OK;
+}
+
+int tables(uint32_t p, hipStream_t s, Tables* out) {
+  int dev;
+  if (current_device(&dev)) return RLX_EHIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_pair(dev, p);
+  auto it = g_tables.find(key);
+  if (it != g_tables.end()) {
+    *out = it->second;
+    return RLX_OK;
+  }
+  Tables t;
+  if (hipMalloc(&t.T, TAB_WORDS * sizeof(uint32_t)) != hipSuccess) return RLX_ENOMEM;
+  if (hipMalloc(&t.C, FOLD_WORDS * sizeof(uint32_t)) != hipSuccess) {
+    (void)hipFree(t.T);
+    return RLX_ENOMEM;
+  }
+  k_tab_base<<<1, 64, 0, s>>>(t.T, p);
+  const int fill = TAB_ROWS * (TAB_COLS - 2);
+  k_tab_fill<<<(fill + 63) / 64, 64, 0, s>>>(t.T);
+  k_tab_fold<<<1, 64, 0, s>>>(t.T, t.C);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+    (void)hipFree(t.T);
+    (void)hipFree(t.C);
+    return RLX_EHIP;
+  }
+  g_tables[key] = t;
+  *out = t;
+  return RLX_OK;
+}
+
+template <bool F64, bool TRACE>
+int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint64_t* trace,
+                  uint64_t trace_steps, uint32_t p, void* stream, int force_general) {
+  if (n == 0 || count == 0) return RLX_OK;
+  if (!states || !out || !valid_p(p)) return RLX_EINVAL;
+  if (!aligned(states, 16) || !aligned(out, 8)) return RLX_EINVAL;
+  if (count > UINT64_MAX / 8 / n) return RLX_EINVAL;
+  if (TRACE) {
+    if (!trace || !aligned(trace, 8)) return RLX_EINVAL;
+    if (count > UINT64_MAX - 11) return RLX_EINVAL;
+    const uint64_t need = (11 + count) / 12 + 1;
+    if (trace_steps < need || trace_steps > UINT64_MAX / 72 / n) return RLX_EINVAL;
+  }
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  hipStream_t s = as_stream(stream);
+  Tables t;
+  int rc = tables(p, s, &t);
+  if (rc) return rc;
+  uint32_t* err;
+  rc = error_word(s, &err);
+  if (rc) return rc;
+  k_generate<F64, TRACE><<<grid, BLOCK, 0, s>>>(states, n, count, out, trace, trace_steps, t.C, p, err,
+                                                force_general);
+  return launch_status();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rlx_strerror(int code) {
+  switch (code) {
+    case RLX_OK: return "ok";
+    case RLX_EINVAL: return "invalid argument";
+    case RLX_EHIP: return "HIP runtime or launch error";
+    case RLX_ENOMEM: return "device allocation failed";
+    case RLX_ESTATE: return "invalid stream record found on the device";
+    default: return "unknown error";
+  }
+}
+
+const char* rlx_version(void) { return "rlx 0.1 gfx950"; }
+
+void rlx_constants(uint32_t m_words[18], uint32_t a_words[18]) {
+  static const uint32_t a[18] = {0x00000001u, 0, 0, 0, 0, 0, 0x01000000u, 0xFFFF0000u,
+                                 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu,
+                                 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFEFFu};
+  for (int k = 0; k < 18; ++k) {
+    if (m_words) m_words[k] = m_word(k);
+    if (a_words) a_words[k] = a[k];
+  }
+}
+
+int rlx_prepare(uint32_t p, void* stream) {
+  if (!valid_p(p)) return RLX_EINVAL;
+  Tables t;
+  int rc = tables(p, as_stream(stream), &t);
+  if (rc) return rc;
+  uint32_t* err;
+  return error_word(as_stream(stream), &err);
+}
+
+int rlx_init_streams(rlx_state* states, uint64_t n, const uint64_t* ids, uint64_t id0, uint32_t p,
+                     void* stream) {
+  if (n == 0) return RLX_OK;
+  if (!states || !valid_p(p) || !aligned(states, 16)) return RLX_EINVAL;
+  if (ids && !aligned(ids, 8)) return RLX_EINVAL;
+  if (!ids && id0 > UINT64_MAX - (n - 1)) return RLX_EINVAL;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  hipStream_t s = as_stream(stream);
+  Tables t;
+  int rc = tables(p, s, &t);
+  if (rc) return rc;
+  k_init<<<grid, BLOCK, 0, s>>>(states, n, ids, id0, p, t.T);
+  return launch_status();
+}
+
+int rlx_skip(rlx_state* states, uint64_t n, const uint64_t* steps, uint64_t steps0, uint32_t p,
+             void* stream) {
+  if (n == 0) return RLX_OK;
+  if (!states || !valid_p(p) || !aligned(states, 16)) return RLX_EINVAL;
+  if (steps && !aligned(steps, 8)) return RLX_EINVAL;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  hipStream_t s = as_stream(stream);
+  Tables t;
+  int rc = tables(p, s, &t);
+  if (rc) return rc;
+  uint32_t* err;
+  rc = error_word(s, &err);
+  if (rc) return rc;
+  k_skip<<<grid, BLOCK, 0, s>>>(states, n, steps, steps0, p, t.T, err);
+  return launch_status();
+}
+
+int rlx_generate_f64(rlx_state* states, uint64_t n, uint64_t count, double* out, uint32_t p,
+                     void* stream) {
+  return generate_impl<true, false>(states, n, count, out, nullptr, 0, p, stream, 0);
+}
+
+int rlx_generate_u64(rlx_state* states, uint64_t n, uint64_t count, uint64_t* out, uint32_t p,
+                     void* stream) {
+  return generate_impl<false, false>(states, n, count, out, nullptr, 0, p, stream, 0);
+}
+
+int rlx_generate_f64_trace(rlx_state* states, uint64_t n, uint64_t count, double* out, uint64_t* trace,
+                           uint64_t steps_per_stream, uint32_t p, void* stream) {
+  if (n != 0 && count != 0 && !trace) return RLX_EINVAL;
+  return generate_impl<true, true>(states, n, count, out, trace, steps_per_stream, p, stream, 0);
+}
+
+int rlx_test_generate_u64_general(rlx_state* states, uint64_t n, uint64_t count, uint64_t* out,
+                                  uint32_t p, void* stream) {
+  return generate_impl<false, false>(states, n, count, out, nullptr, 0, p, stream, 1);
+}
+
+int rlx_check_errors(void* stream, uint32_t* flags) {
+  hipStream_t s = as_stream(stream);
+  uint32_t* err;
+  int rc = error_word(s, &err);
+  if (rc) return rc;
+  if (hipStreamSynchronize(s) != hipSuccess) return RLX_EHIP;
+  uint32_t h = 0;
+  if (hipMemcpy(&h, err, sizeof h, hipMemcpyDeviceToHost) != hipSuccess) return RLX_EHIP;
+  if (h && hipMemset(err, 0, sizeof h) != hipSuccess) return RLX_EHIP;
+  if (flags) *flags = h;
+  return h ? RLX_ESTATE : RLX_OK;
+}
+
+int rlx_test_mulmod(const uint64_t* x, const uint64_t* y, uint64_t* out, uint64_t n, void* stream) {
+  if (n == 0) return RLX_OK;
+  if (!x || !y || !out) return RLX_EINVAL;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  k_test_mulmod<<<grid, BLOCK, 0, as_stream(stream)>>>(x, y, out, n);
+  return launch_status();
+}
+
+int rlx_test_pow(const uint64_t* base, const uint64_t* exps, uint64_t* out, uint64_t n, void* stream) {
+  if (n == 0) return RLX_OK;
+  if (!base || !exps || !out) return RLX_EINVAL;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  k_test_pow<<<grid, BLOCK, 0, as_stream(stream)>>>(base, exps, out, n);
+  return launch_status();
+}
+
+int rlx_test_to_ranlux(const uint64_t* x, uint64_t* d, uint32_t* carry, uint64_t n, void* stream) {
+  if (n == 0) return RLX_OK;
+  if (!x || !d || !carry) return RLX_EINVAL;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  k_test_to_ranlux<<<grid, BLOCK, 0, as_stream(stream)>>>(x, d, carry, n);
+  return launch_status();
+}
+
+}  // extern "C"

@@ -1,0 +1,382 @@
+// rlx_arith.hpp -- 576-bit modular arithmetic of RANLUX++ for gfx950.
+//
+// Numbers below 2^576 are held as eighteen 32-bit words, least significant
+// first.  The modulus is m = 2^576 - 2^240 + 1 (paper, section 2.2).  Two
+// multiplications modulo m exist:
+//
+//  * mulmod_generic(x, y): the full 576 x 576 -> 1152-bit product (section
+//    2.1) followed by a reduction that uses only additions, subtractions and
+//    shifts and ends with the fix that makes the result smaller than m
+//    (section 2.2).  Used for seeding, skipping and table construction, where
+//    the multiplier differs per lane.
+//
+//  * step(): the generator step X <- A X mod m for a multiplier A that is the
+//    same for the whole launch.  The reduction is folded into a constant
+//    table: C_j = A 2^(27 j) mod m (j < 22), so that with X split into 22
+//    limbs l_j of 27 bits, A X = sum_j l_j C_j (mod m).  Each product
+//    l_j * C_j[k] is below 2^59 and every column sum of 22 of them is below
+//    2^64, so the product runs on v_mad_u64_u32 with no carry handling; one
+//    32-bit word remains above 2^576 and is folded with 2^576 = 2^240 - 1
+//    (mod m).
+//
+// Both end in the canonical residue.  Rare carries, borrows and the final
+// comparison with m take a general branch that is exact for every input; the
+// common case is a short straight-line path.  `force_general` sends every
+// lane through the general code (used by tests).
+//
+// The conversion to RANLUX numbers (section 2.3) uses
+//   D = floor(X 2^576 / m) = X + q0 - delta,   q0 = floor(X / 2^336),
+// where, with D' = X + q0, delta = 1 exactly when D' m > X 2^576, i.e. when
+// D' > u 2^240 for u = (X mod 2^336) + q0.  If u >= 2^336 then delta = 0;
+// otherwise u = D' mod 2^336 and delta = 1 iff floor(D' / 2^240) > D' mod
+// 2^336, or they are equal and D' mod 2^240 != 0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define RLX_HD __host__ __device__ __forceinline__
+
+namespace rlx {
+
+constexpr int NW = 18;        // 32-bit words of a 576-bit number
+constexpr int NL = 22;        // 27-bit limbs of X in the constant-multiplier step
+constexpr int LB = 27;        // limb bits
+constexpr uint32_t LMASK = (1u << LB) - 1u;
+
+// m = 2^576 - 2^240 + 1
+RLX_HD uint32_t m_word(int k) {
+  return k == 0 ? 1u : (k < 7 ? 0u : (k == 7 ? 0xFFFF0000u : 0xFFFFFFFFu));
+}
+
+// ---------------------------------------------------------------------------
+// word helpers
+
+RLX_HD uint32_t addc(uint32_t a, uint32_t b, uint32_t& c) {
+  uint64_t s = (uint64_t)a + b + c;
+  c = (uint32_t)(s >> 32);
+  return (uint32_t)s;
+}
+
+RLX_HD uint32_t subb(uint32_t a, uint32_t b, uint32_t& br) {
+  uint64_t d = (uint64_t)a - (uint64_t)b - (uint64_t)br;
+  br = (uint32_t)(d >> 63);
+  return (uint32_t)d;
+}
+
+// bits [32 i + s, 32 i + s + 32) of the number w (s in 0..31), reading zeros
+// above word n-1.
+template <int N>
+RLX_HD uint32_t window32(const uint32_t (&w)[N], int i, int s) {
+  uint32_t lo = (i < N) ? w[i] : 0u;
+  if (s == 0) return lo;
+  uint32_t hi = (i + 1 < N) ? w[i + 1] : 0u;
+  return (lo >> s) | (hi << (32 - s));
+}
+
+// x >= m for a number x < 2^576 held in NW words.
+RLX_HD bool geq_m(const uint32_t (&x)[NW]) {
+  uint32_t br = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) (void)subb(x[k], m_word(k), br);
+  return br == 0;
+}
+
+// x <- x - m if x >= m (x < 2^576 < 2m, so one subtraction suffices).
+RLX_HD void canonicalize(uint32_t (&x)[NW]) {
+  uint32_t r[NW];
+  uint32_t br = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) r[k] = subb(x[k], m_word(k), br);
+  const bool ge = (br == 0);
+#pragma unroll
+  for (int k = 0; k < NW; ++k) x[k] = ge ? r[k] : x[k];
+}
+
+// x <- x + h 2^240 - h (mod m) for x < 2^576 and h < 2^32, exact and
+// canonical: the value x + h (2^240 - 1) is non-negative and below
+// 2^576 + 2^272; an overflow above 2^576 is folded once more.
+RLX_HD void fold_word_general(uint32_t (&x)[NW], uint32_t h) {
+  // t = x + (h << 16) at word 7 - h at word 0, as a signed running sum
+  int64_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    int64_t add = 0;
+    if (k == 7) add = (int64_t)(uint64_t)(h << 16);
+    if (k == 8) add = (int64_t)(h >> 16);
+    if (k == 0) add = -(int64_t)h;
+    acc += (int64_t)x[k] + add;
+    x[k] = (uint32_t)acc;
+    acc >>= 32;  // arithmetic: carry in {-1, 0, 1}
+  }
+  // the sum is >= 0, so the final carry is 0 or 1
+  uint32_t top = (uint32_t)acc;
+  // x + top 2^576 = x + top (2^240 - 1) (mod m); when top = 1, x < 2^272 here
+  // and no further overflow occurs.  2^240 enters as 2^16 at word 7.
+  uint32_t c = top << 16;
+#pragma unroll
+  for (int k = 7; k < NW; ++k) x[k] = addc(x[k], 0u, c);
+  uint32_t br = top;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) x[k] = subb(x[k], 0u, br);
+  canonicalize(x);
+}
+
+// ---------------------------------------------------------------------------
+// generic multiplication modulo m (sections 2.1, 2.2)
+
+// p = x * y, 36 words.  Column sums of up to 18 products of 64 bits are
+// accumulated in 64 bits plus a carry count.
+RLX_HD void mul576(const uint32_t (&x)[NW], const uint32_t (&y)[NW], uint32_t (&p)[2 * NW]) {
+  uint64_t acc = 0;
+  uint32_t top = 0;
+#pragma unroll
+  for (int k = 0; k < 2 * NW - 1; ++k) {
+    const int ilo = k < NW ? 0 : k - NW + 1;
+    const int ihi = k < NW ? k : NW - 1;
+#pragma unroll
+    for (int i = ilo; i <= ihi; ++i) {
+      uint64_t t = (uint64_t)x[i] * y[k - i];
+      acc += t;
+      top += (acc < t) ? 1u : 0u;
+    }
+    p[k] = (uint32_t)acc;
+    acc = (acc >> 32) | ((uint64_t)top << 32);
+    top = 0;
+  }
+  p[2 * NW - 1] = (uint32_t)acc;
+}
+
+// r = p mod m for p < 2^1152 (36 words).  With L = p mod 2^576 and
+// H = p >> 576:  p = L + H 2^240 - H (mod m), applied until the value fits
+// in 576 bits, then the final comparison with m.
+RLX_HD void mod_m(const uint32_t (&p)[2 * NW], uint32_t (&r)[NW]) {
+  // T1 = L + H 2^240 - H  (>= 0, < 2^817): 26 words
+  uint32_t t1[26];
+  {
+    int64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < 26; ++k) {
+      int64_t v = acc;
+      if (k < NW) v += (int64_t)p[k] - (int64_t)p[NW + k];
+      if (k >= 7) {
+        // (H << 16) word k - 7: bits [32 (k-7) - 16, 32 (k-7) + 16) of H
+        const int j = k - 7;
+        uint32_t lo = (j >= 1 && j - 1 < NW) ? p[NW + j - 1] : 0u;
+        uint32_t hi = (j < NW) ? p[NW + j] : 0u;
+        v += (int64_t)(uint64_t)((lo >> 16) | (hi << 16));
+      }
+      t1[k] = (uint32_t)v;
+      acc = v >> 32;
+    }
+  }
+  // T2 = T1 mod 2^576 + T1hi 2^240 - T1hi, T1hi = words 18..25 (< 2^241)
+  uint32_t t2[NW + 1];
+  {
+    int64_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < NW + 1; ++k) {
+      int64_t v = acc;
+      if (k < NW) v += (int64_t)t1[k];
+      if (k < 8) v -= (int64_t)t1[NW + k];
+      if (k >= 7 && k <= 16) {
+        const int j = k - 7;  // word j of (T1hi << 16), T1hi has 8 words
+        uint32_t lo = (j >= 1 && j - 1 < 8) ? t1[NW + j - 1] : 0u;
+        uint32_t hi = (j < 8) ? t1[NW + j] : 0u;
+        v += (int64_t)(uint64_t)((lo >> 16) | (hi << 16));
+      }
+      t2[k] = (uint32_t)v;
+      acc = v >> 32;
+    }
+  }
+  // T3 = T2 mod 2^576 + t (2^240 - 1), t = T2 >> 576 in {0, 1}; then < m
+#pragma unroll
+  for (int k = 0; k < NW; ++k) r[k] = t2[k];
+  const uint32_t t = t2[NW];
+  {
+    uint32_t c = t << 16;
+#pragma unroll
+    for (int k = 7; k < NW; ++k) r[k] = addc(r[k], 0u, c);
+    uint32_t br = t;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) r[k] = subb(r[k], 0u, br);
+  }
+  canonicalize(r);
+}
+
+RLX_HD void mulmod_generic(const uint32_t (&x)[NW], const uint32_t (&y)[NW], uint32_t (&r)[NW]) {
+  uint32_t p[2 * NW];
+  mul576(x, y, p);
+  mod_m(p, r);
+}
+
+// ---------------------------------------------------------------------------
+// the generator step with a launch-uniform multiplier
+
+// 22 limbs of 27 bits of X (< 2^576: the top limb has 9 bits).
+RLX_HD void unpack27(const uint32_t (&w)[NW], uint32_t (&l)[NL]) {
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    const int bit = LB * j;
+    l[j] = window32(w, bit >> 5, bit & 31) & LMASK;
+  }
+}
+
+// Identity map of a table offset; kernels pass one that hides the offset
+// from the optimiser (see step()).
+struct Plain {
+  RLX_HD uint32_t operator()(uint32_t v) const { return v; }
+};
+
+// X <- A X mod m.  `tab` holds C_j = A 2^(27 j) mod m, row j = 18 words.
+// Returns through `x` the canonical residue.
+template <class Launder = Plain>
+RLX_HD void step(uint32_t (&x)[NW], const uint32_t* __restrict__ tab, bool force_general,
+                 Launder launder = Launder()) {
+  uint32_t l[NL];
+  unpack27(x, l);
+  uint64_t s[NW];
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    // Row j of the table is read with scalar loads right before its 18
+    // multiply-adds.  On the GPU `launder` makes the row offset opaque, so
+    // the compiler cannot hoist all 396 table words into scalar registers
+    // at once (they do not fit).
+    const uint32_t* __restrict__ row = tab + launder((uint32_t)(j * NW));
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const uint64_t prod = (uint64_t)l[j] * row[k];
+      s[k] = j == 0 ? prod : s[k] + prod;
+    }
+  }
+  // carry-normalise to 18 words plus the word h above 2^576
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    uint64_t v = s[k] + c;
+    x[k] = (uint32_t)v;
+    c = (uint32_t)(v >> 32);
+  }
+  const uint32_t h = c;
+  // fast fold: x - h at words 0-1, x + (h << 16) at words 7-9
+  uint32_t br = 0;
+  const uint32_t f0 = subb(x[0], h, br);
+  const uint32_t f1 = subb(x[1], 0u, br);
+  uint32_t cy = 0;
+  const uint32_t f7 = addc(x[7], h << 16, cy);
+  const uint32_t f8 = addc(x[8], h >> 16, cy);
+  const uint32_t f9 = addc(x[9], 0u, cy);
+  // rare: a borrow or carry that runs further, or a result that may be >= m
+  const bool rare = (br | cy) != 0 || x[17] == 0xFFFFFFFFu || force_general;
+  if (rare) {
+    fold_word_general(x, h);
+  } else {
+    x[0] = f0; x[1] = f1; x[7] = f7; x[8] = f8; x[9] = f9;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// conversion to RANLUX numbers (section 2.3)
+
+// d = floor(X 2^576 / m) for canonical X (the 24 RANLUX numbers, oldest in
+// the least significant 24 bits).
+RLX_HD void to_ranlux_general(const uint32_t (&x)[NW], uint32_t (&d)[NW]) {
+  // q0 = X >> 336 (240 bits, 8 words), D' = X + q0
+  uint32_t q[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) q[i] = window32(x, 10 + i, 16);
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) d[k] = addc(x[k], k < 8 ? q[k] : 0u, c);
+  // e = carry out of bit 336 in (X mod 2^336) + q0
+  uint32_t c2 = 0;
+  uint32_t top = 0;
+#pragma unroll
+  for (int k = 0; k < 11; ++k) {
+    uint32_t xv = (k < 10) ? x[k] : (x[10] & 0xFFFFu);
+    top = addc(xv, k < 8 ? q[k] : 0u, c2);
+  }
+  const uint32_t e = (top >> 16) & 1u;
+  // hi = D' >> 240 and lo = D' mod 2^336 (11 words each); z = [D' mod 2^240 == 0]
+  uint32_t zacc = 0;
+#pragma unroll
+  for (int k = 0; k < 7; ++k) zacc |= d[k];
+  zacc |= d[7] & 0xFFFFu;
+  uint32_t br = (zacc == 0) ? 1u : 0u;
+#pragma unroll
+  for (int k = 0; k < 11; ++k) {
+    uint32_t hi = window32(d, 7 + k, 16);
+    uint32_t lo = (k < 10) ? d[k] : (d[10] & 0xFFFFu);
+    (void)subb(hi, lo, br);
+  }
+  const uint32_t delta = (e == 0 && br == 0) ? 1u : 0u;
+  uint32_t b2 = delta;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) d[k] = subb(d[k], 0u, b2);
+}
+
+RLX_HD void to_ranlux(const uint32_t (&x)[NW], uint32_t (&d)[NW], bool force_general) {
+  // fast path: the carry of X + q0 stops by word 8, the top 32 bits of
+  // D' >> 240 and D' mod 2^336 differ, and subtracting delta does not borrow
+  // past word 0.
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) d[k] = addc(x[k], window32(x, 10 + k, 16), c);
+  d[8] = addc(x[8], 0u, c);
+#pragma unroll
+  for (int k = 9; k < NW; ++k) d[k] = x[k];
+  const uint32_t hi32 = x[17];
+  const uint32_t lo32 = window32(x, 9, 16);
+  const uint32_t delta = hi32 > lo32 ? 1u : 0u;
+  const bool rare = c != 0 || hi32 == lo32 || (delta != 0 && d[0] == 0) || force_general;
+  if (rare) {
+    to_ranlux_general(x, d);
+  } else {
+    d[0] -= delta;
+  }
+}
+
+// RANLUX carry bit c = X - D + floor(D / 2^336) (0 or 1) for canonical X and
+// D = to_ranlux(X).
+RLX_HD uint32_t ranlux_carry(const uint32_t (&x)[NW], const uint32_t (&d)[NW]) {
+  // X - D + (D >> 336) is 0 or 1: only the lowest word matters once the
+  // value is known to be that small.
+  uint32_t lo = x[0] - d[0] + window32(d, 10, 16);
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// 48-bit fields (section 2.3)
+
+// field k (0..11) of D as (low 32 bits, high 16 bits)
+RLX_HD void field(const uint32_t (&d)[NW], int k, uint32_t& lo, uint32_t& hi) {
+  const int i = k >> 1;
+  if ((k & 1) == 0) {
+    lo = d[3 * i];
+    hi = d[3 * i + 1] & 0xFFFFu;
+  } else {
+    lo = (d[3 * i + 1] >> 16) | (d[3 * i + 2] << 16);
+    hi = d[3 * i + 2] >> 16;
+  }
+}
+
+RLX_HD uint64_t field_u64(const uint32_t (&d)[NW], int k) {
+  uint32_t lo, hi;
+  field(d, k, lo, hi);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// v 2^-48 for a 48-bit v: 1 + v 2^-48 has v as the top 48 of its 52 mantissa
+// bits; subtracting 1.0 is exact.
+RLX_HD double field_f64(const uint32_t (&d)[NW], int k) {
+  uint32_t lo, hi;
+  field(d, k, lo, hi);
+  const uint32_t bhi = 0x3FF00000u | (hi << 4) | (lo >> 28);
+  const uint32_t blo = lo << 4;
+  const uint64_t bits = ((uint64_t)bhi << 32) | blo;
+  double one_plus;
+  __builtin_memcpy(&one_plus, &bits, 8);
+  return one_plus - 1.0;
+}
+
+}  // namespace rlx

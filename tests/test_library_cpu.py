@@ -1,0 +1,69 @@
+"""Host-side checks of librlx.so that need no GPU: it loads, it exports every
+symbol the public header declares, and its constants are the paper's."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rlx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rlx_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def rlx():
+    import paper_2106_02504_amd as r
+    return r
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for need in ("rlx_init_streams", "rlx_skip", "rlx_generate_f64", "rlx_generate_u64"):
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol(rlx):
+    lib = rlx.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    # and the binding declares a signature for each of them
+    from paper_2106_02504_amd import _SIGS
+    assert sorted(_SIGS) == declared_functions()
+
+
+def test_library_constants_match_the_paper(rlx):
+    m, a = rlx.constants()
+    assert m == 2 ** 576 - 2 ** 240 + 1 == O.M
+    assert a == O.A and (a << 24) % m == 1
+
+
+def test_strerror_and_version(rlx):
+    lib = rlx.lib()
+    assert lib.rlx_strerror(0) == b"ok"
+    assert b"invalid" in lib.rlx_strerror(1)
+    assert lib.rlx_version().startswith(b"rlx")
+
+
+def test_invalid_arguments_fail_before_any_device_work(rlx):
+    lib = rlx.lib()
+    # NULL states with n > 0, bad luxury levels, misaligned pointers
+    assert lib.rlx_init_streams(None, 5, None, 0, 2048, None) == 1
+    assert lib.rlx_generate_f64(None, 5, 10, None, 2048, None) == 1
+    assert lib.rlx_skip(ctypes.c_void_p(16), 5, None, 0, 23, None) == 1
+    assert lib.rlx_generate_u64(ctypes.c_void_p(8), 5, 10, ctypes.c_void_p(16), 2048, None) == 1
+    assert lib.rlx_generate_f64(ctypes.c_void_p(16), 5, 10, ctypes.c_void_p(12), 2048, None) == 1
+    assert lib.rlx_prepare(10, None) == 1
+    # overflow of n * count
+    assert lib.rlx_generate_f64(ctypes.c_void_p(16), 1 << 40, 1 << 40, ctypes.c_void_p(16), 2048, None) == 1
+    # no-ops
+    assert lib.rlx_generate_f64(None, 0, 10, None, 2048, None) == 0
+    assert lib.rlx_generate_u64(None, 5, 0, None, 2048, None) == 0
+    assert lib.rlx_skip(None, 0, None, 0, 2048, None) == 0
