@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark of the RANLUX++ generator hot path on one MI355X.
+
+One bench step is one pass of the plain hot path over the many-streams
+workload: seed 65 536 streams (ids 0..65535, luxury p = 2048) on the GPU by
+exponentiation, then draw 4096 float64 uniforms per stream (2^28 doubles,
+2 GiB) into a stream-major [65536, 4096] array in HBM.  The value reported is
+doubles/s over whole steps.
+
+Other legs (reported beside the headline in the same JSON line):
+  u64        the same step writing the 48-bit integers instead of doubles
+  single     one stream (id 1), 2^20 doubles plus the state after each step
+  skip       2^20 seeded states, each skipped by a log-uniform offset in
+             [1, 2^64) generator steps
+  cpu_baseline  the CPU oracle (Python integers) on a bounded sample of the
+             many-streams workload, on a process pool; its values are also
+             compared bit for bit with the GPU's output of the same streams.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import multiprocessing as mp
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+P = 2048
+N_STREAMS = 65536
+DRAWS = 4096
+HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
+VALU_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (full-rate 32-bit ops)
+MADS_PER_DOUBLE = 27              # 18 x 18 32-bit multiply-adds per step / 12 doubles
+KERNEL_SOURCES = ("paper_2106_02504_amd/csrc/rlx.hip", "paper_2106_02504_amd/csrc/rlx_arith.hpp")
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, on a pool of processes
+
+def _oracle_chunk(args):
+    lo, hi, p, count = args
+    import numpy as np
+    import oracle as O
+    out = np.empty((hi - lo, count), dtype=np.uint64)
+    for r, sid in enumerate(range(lo, hi)):
+        vals, _, _ = O.draws(O.seed(sid, p), 0, p, count)
+        out[r] = vals
+    return lo, out
+
+
+def cpu_baseline(n_streams: int, workers: int):
+    import numpy as np
+    chunk = max(1, n_streams // (workers * 8))
+    tasks = [(lo, min(n_streams, lo + chunk), P, DRAWS) for lo in range(0, n_streams, chunk)]
+    res = np.empty((n_streams, DRAWS), dtype=np.uint64)
+    ctx = mp.get_context("fork")  # forked before any GPU use in this process
+    t0 = time.perf_counter()
+    with ctx.Pool(workers) as pool:
+        for lo, arr in pool.imap_unordered(_oracle_chunk, tasks):
+            res[lo:lo + arr.shape[0]] = arr
+    dt = time.perf_counter() - t0
+    return res, dt
+
+
+# ---------------------------------------------------------------------------
+
+def sources_sha() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        doc = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    ent = doc.get(kernel)
+    if not ent or ent.get("sources_sha") != sources_sha():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def timed(fn, stream, steps, warmup, torch):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--cpu-streams", type=int, default=8192)
+    ap.add_argument("--legs", default="u64,single,skip", help="extra legs to time (comma list or 'none')")
+    ap.add_argument("--lanes", type=int, default=0, help="force lanes per stream (0 = library's pick)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
+              "the streams are independent and the multi-GPU sharding is described in DESIGN.md",
+              file=sys.stderr)
+        return 2
+
+    cpu = None
+    if not args.no_cpu:
+        workers = min(16, os.cpu_count() or 1)
+        ref, cpu_dt = cpu_baseline(args.cpu_streams, workers)
+        cpu = {"value": args.cpu_streams * DRAWS / cpu_dt, "unit": "doubles/s", "cores": workers,
+               "kind": "oracle",
+               "sample": f"first {args.cpu_streams} of the 65536 streams x {DRAWS} doubles, p={P} "
+                         f"({args.cpu_streams * DRAWS} doubles, {cpu_dt:.1f} s wall on {workers} processes)"}
+
+    import numpy as np
+    import torch
+    import paper_2106_02504_amd as rlx
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    rlx.prepare(P)
+    rlx.set_lanes_per_stream(args.lanes)
+    lanes = rlx.lanes_per_stream(N_STREAMS, DRAWS)
+    st = rlx.new_states(N_STREAMS, device=dev)
+    out = torch.empty((N_STREAMS, DRAWS), dtype=torch.float64, device=dev)
+
+    ev = []
+
+    def step():
+        rlx.init_streams(st, P, id0=0)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        rlx.generate_f64(st, DRAWS, P, out=out)
+        e1.record(stream)
+        ev.append((e0, e1))
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev.clear()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / args.steps
+    gen_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    total = N_STREAMS * DRAWS
+    value = total / wall
+
+    # bit-exact check of the sampled streams against the oracle's values
+    bit_exact = None
+    if cpu is not None:
+        got = (out[: args.cpu_streams] * 2.0 ** 48).to(torch.int64).cpu().numpy().view(np.uint64)
+        bit_exact = bool(np.array_equal(got, ref))
+        cpu["bit_exact_vs_gpu"] = bit_exact
+
+    # roofline of the generation kernel: output doubles + state read/write
+    bytes_per_launch = total * 8 + N_STREAMS * 80 * 2
+    achieved_gbs = bytes_per_launch / (gen_ms * 1e-3) / 1e9
+    traffic = measured_traffic("k_generate_f64_many_streams")
+    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "k_generate<f64>", "kernel_ms": round(gen_ms, 4),
+                "algorithmic_bytes_per_launch": bytes_per_launch}
+    mads = total * MADS_PER_DOUBLE
+    roofline_alu = {"bound": "alu", "achieved": round(mads / (gen_ms * 1e-3) / 1e12, 2),
+                    "peak": round(VALU_LANE_OPS / 1e12, 2), "unit": "Tmad/s",
+                    "frac": round(mads / (gen_ms * 1e-3) / VALU_LANE_OPS, 4),
+                    "note": "27 32x32->64 multiply-adds per double (schoolbook 18x18 words per 12 doubles) "
+                            "against one full-rate 32-bit VALU op per lane per cycle"}
+
+    legs = {}
+    wanted = set() if args.legs == "none" else set(args.legs.split(","))
+    if "u64" in wanted:
+        outu = torch.empty((N_STREAMS, DRAWS), dtype=torch.int64, device=dev)
+
+        def step_u():
+            rlx.init_streams(st, P, id0=0)
+            rlx.generate_u64(st, DRAWS, P, out=outu)
+        dt = timed(step_u, stream, max(5, args.steps // 2), 2, torch)
+        legs["u64"] = {"value": total / dt, "unit": "values/s", "ms_per_step": dt * 1e3,
+                       "same_bits_as_f64": bool(torch.equal(outu.to(torch.float64) * 2.0 ** -48, out))}
+        del outu
+    if "single" in wanted:
+        st1 = rlx.new_states(1, device=dev)
+
+        def step_1():
+            rlx.init_streams(st1, P, id0=1)
+            rlx.generate_f64_trace(st1, 1 << 20, P)
+        dt = timed(step_1, stream, 5, 2, torch)
+        legs["single"] = {"value": (1 << 20) / dt, "unit": "doubles/s", "ms_per_step": dt * 1e3,
+                          "lanes_per_stream": rlx.lanes_per_stream(1, 1 << 20),
+                          "workload": "1 stream (id 1), p=2048, 2^20 doubles + state after each step"}
+    if "skip" in wanted:
+        import workloads
+        n3 = 1 << 20
+        st3 = rlx.new_states(n3, device=dev)
+        offs = torch.from_numpy(workloads.skip_offsets(n3).view(np.int64)).to(dev)
+        rlx.init_streams(st3, P, id0=0)
+
+        def step_3():
+            rlx.skip(st3, offs, P)
+        dt = timed(step_3, stream, 10, 2, torch)
+        legs["skip"] = {"value": n3 / dt, "unit": "states/s", "ms_per_step": dt * 1e3,
+                        "workload": "2^20 states, offsets log-uniform in [1, 2^64) steps"}
+        del st3, offs
+
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        b.copy_(a)
+        torch.cuda.synchronize()
+
+    rec = {
+        "metric": "doubles/sec (1 GPU, bit-exact vs oracle), plain vs batched; p99 request latency",
+        "value": value,
+        "unit": "doubles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "many-streams: 65536 streams seeded with ids 0..65535 by skip-ahead "
+                               "seeding, p=2048, 4096 float64 per stream (2^28 doubles) stream-major in HBM",
+                   "streams": N_STREAMS, "draws_per_stream": DRAWS, "p": P, "output": "float64",
+                   "lanes_per_stream": lanes},
+        "bit_exact": bit_exact,
+        "roofline": roofline,
+        "roofline_alu": roofline_alu,
+        "cpu_baseline": cpu,
+        "legs": legs,
+        "kernel_sources_sha": sources_sha(),
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

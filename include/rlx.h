@@ -129,6 +129,17 @@ int rlx_generate_f64_trace(rlx_state *states, uint64_t n, uint64_t count,
                            double *out, uint64_t *trace,
                            uint64_t steps_per_stream, uint32_t p, void *stream);
 
+/* Lanes per stream record used by the generate calls.  G lanes of one
+ * record interleave its generator steps (lane l takes steps l, l + G, ...,
+ * advancing by the launch-uniform multiplier A_p^G), and their values are
+ * staged through LDS so that stores write contiguous runs of the output row.
+ * By default G is picked from n and count (rlx_lanes_per_stream reports the
+ * pick); rlx_set_lanes_per_stream(G) forces a power of two G <= 4096 for all
+ * later calls in the process (0 restores the automatic pick).  The values
+ * produced never depend on G. */
+int rlx_set_lanes_per_stream(uint32_t lanes);
+uint32_t rlx_lanes_per_stream(uint64_t n, uint64_t count);
+
 /* Synchronise `stream`, then read and clear the device error word of the
  * current device: *flags receives the RLX_ERR_* bits set by kernels since
  * the last call.  Returns RLX_ESTATE if any bit was set. */

@@ -25,6 +25,7 @@ import torch  # load torch's HIP runtime first: librlx.so binds to the same one
 __all__ = [
     "RlxError", "lib", "new_states", "prepare", "init_streams", "skip",
     "generate_f64", "generate_u64", "generate_f64_trace", "check_errors",
+    "set_lanes_per_stream", "lanes_per_stream",
     "constants", "test_mulmod", "test_pow", "test_to_ranlux",
     "test_generate_u64_general", "STATE_WORDS",
 ]
@@ -48,6 +49,8 @@ _SIGS = {
     "rlx_generate_u64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_f64_trace": (_int, [_vp, _u64, _u64, _vp, _vp, _u64, _u32, _vp]),
     "rlx_check_errors": (_int, [_vp, ctypes.POINTER(_u32)]),
+    "rlx_set_lanes_per_stream": (_int, [_u32]),
+    "rlx_lanes_per_stream": (_u32, [_u64, _u64]),
     "rlx_constants": (None, [ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "rlx_test_mulmod": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "rlx_test_pow": (_int, [_vp, _vp, _vp, _u64, _vp]),
@@ -179,6 +182,17 @@ def generate_f64_trace(states: torch.Tensor, count: int, p: int):
         _check(lib().rlx_generate_f64_trace(states.data_ptr(), n, count, out.data_ptr(), trace.data_ptr(),
                                             steps, p, _stream()), "rlx_generate_f64_trace")
     return out, trace
+
+
+def set_lanes_per_stream(lanes: int) -> None:
+    """Force G lanes per record for later generate calls (power of two
+    <= 4096); 0 restores the automatic choice.  Values never depend on G."""
+    _check(lib().rlx_set_lanes_per_stream(lanes), "rlx_set_lanes_per_stream")
+
+
+def lanes_per_stream(n: int, count: int) -> int:
+    """The G a generate call with n records and `count` values would use."""
+    return int(lib().rlx_lanes_per_stream(n, count))
 
 
 def check_errors() -> int:

@@ -32,7 +32,8 @@ constexpr int TAB_ROWS = 40;
 constexpr int TAB_COLS = 16;
 constexpr int SEED_ROW0 = 24;  // 2^96 = 16^24
 constexpr size_t TAB_WORDS = (size_t)TAB_ROWS * TAB_COLS * NW;
-constexpr size_t FOLD_WORDS = (size_t)NL * NW;
+constexpr int FOLD_G = 13;  // lanes per stream G = 2^g, g < 13 (1 .. 4096)
+constexpr size_t FOLD_WORDS = (size_t)FOLD_G * NL * NW;
 constexpr int BLOCK = 256;
 
 // a = 2^576 - 2^552 - 2^240 + 2^216 + 1 = 2^-24 mod m: one subtract-with-
@@ -100,10 +101,11 @@ __device__ __forceinline__ uint32_t check_record(const uint32_t (&x)[NW], uint32
 }
 
 // Row-offset barrier for the generator step: an empty asm that claims to
-// modify the (scalar) offset, so the table loads using it stay in place.
+// modify the (scalar) offset using a word `dep` of the previous row, so the
+// table load using the offset cannot move above the arrival of that row.
 struct SgprBarrier {
-  __device__ __forceinline__ uint32_t operator()(uint32_t v) const {
-    asm volatile("" : "+s"(v));
+  __device__ __forceinline__ uint32_t operator()(uint32_t v, uint32_t dep) const {
+    asm volatile("" : "+s"(v) : "s"(dep));
     return v;
   }
 };
@@ -156,17 +158,20 @@ __global__ __launch_bounds__(64) void k_tab_fill(uint32_t* __restrict__ T) {
   store_words(T + ((size_t)i * TAB_COLS + j) * NW, r);
 }
 
-// C[j] = A_p 2^(27 j) mod m, one lane per row.
+// C_g[j] = A_p^(2^g) 2^(27 j) mod m: block g (g < FOLD_G) builds the folded
+// multiplier of a step by 2^g generator steps, one lane per row j.  A_p^(2^g)
+// is a single entry of T: 2^g = v 16^i with v in {1, 2, 4, 8}.
 __global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T, uint32_t* __restrict__ C) {
+  const int g = blockIdx.x;
   const int j = threadIdx.x;
   if (j >= NL) return;
   uint32_t a[NW], pw[NW], r[NW];
-  load_words(T + (size_t)1 * NW, a);  // T[0][1] = A_p
+  load_words(T + ((size_t)(g >> 2) * TAB_COLS + (1u << (g & 3))) * NW, a);
   const int bit = LB * j;
 #pragma unroll
   for (int k = 0; k < NW; ++k) pw[k] = (k == (bit >> 5)) ? (1u << (bit & 31)) : 0u;
   mulmod_generic(a, pw, r);
-  store_words(C + (size_t)j * NW, r);
+  store_words(C + ((size_t)g * NL + j) * NW, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -224,13 +229,18 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
 // ---------------------------------------------------------------------------
 // generation (sections 2.1-2.3)
 
+constexpr int FIELDS = 12;
+constexpr int WAVE = 64;
+
 template <bool F64>
-__device__ __forceinline__ void put(void* __restrict__ row, uint64_t j, const uint32_t (&d)[NW], int f) {
+__device__ __forceinline__ uint64_t field_bits(const uint32_t (&d)[NW], int f) {
   if (F64) {
-    reinterpret_cast<double*>(row)[j] = field_f64(d, f);
-  } else {
-    reinterpret_cast<uint64_t*>(row)[j] = field_u64(d, f);
+    const double v = field_f64(d, f);
+    uint64_t b;
+    __builtin_memcpy(&b, &v, 8);
+    return b;
   }
+  return field_u64(d, f);
 }
 
 __device__ __forceinline__ void put_trace(uint64_t* __restrict__ tr, const uint32_t (&x)[NW]) {
@@ -238,64 +248,128 @@ __device__ __forceinline__ void put_trace(uint64_t* __restrict__ tr, const uint3
   for (int k = 0; k < 9; ++k) tr[k] = ((uint64_t)x[2 * k + 1] << 32) | x[2 * k];
 }
 
-// Draw `count` values for every record.  Block t of a record holds the 12
-// fields of the t-th state visited; the value with output index j is field
-// (pos + j) mod 12 of block (pos + j) / 12.  The record is advanced eagerly
-// (pos ends in 0..11).
-template <bool F64, bool TRACE>
-__global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, uint64_t n,
-                                                    uint64_t count, void* __restrict__ out,
-                                                    uint64_t* __restrict__ trace, uint64_t trace_steps,
-                                                    const uint32_t* __restrict__ ctab, uint32_t p,
-                                                    uint32_t* __restrict__ err, int force_general) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  uint32_t x[NW], pos, sp;
-  load_record(st, i, x, pos, sp);
-  const uint32_t bad = check_record(x, pos, sp, p);
-  if (bad) {
-    atomicOr(err, bad);
-    return;
-  }
-  const bool force = force_general != 0;
-  const uint64_t total = pos + count;
-  const uint64_t nadv = total / 12;
-  const uint32_t rem = (uint32_t)(total % 12);
-  char* row = reinterpret_cast<char*>(out) + i * count * 8;
-  uint64_t* tr = TRACE ? trace + i * trace_steps * 9 : nullptr;
-  uint32_t d[NW];
+// LDS writes of a wave become visible to the whole wave.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-  // block 0: fields pos .. min(12, pos + count) - 1
-  if (TRACE) put_trace(tr, x);
-  to_ranlux(x, d, force);
-  {
-    const uint64_t end = total < 12 ? total : 12;
-#pragma unroll
-    for (int f = 0; f < 12; ++f)
-      if ((uint32_t)f >= pos && (uint64_t)f < end) put<F64>(row, (uint64_t)f - pos, d, f);
-  }
-  // full blocks 1 .. nadv - 1
-  uint64_t base = 12 - pos;
-  for (uint64_t t = 1; t < nadv; ++t) {
-    step(x, ctab, force, SgprBarrier());
-    if (TRACE) put_trace(tr + t * 9, x);
-    to_ranlux(x, d, force);
-#pragma unroll
-    for (int f = 0; f < 12; ++f) put<F64>(row, base + f, d, f);
-    base += 12;
-  }
-  // last advance; its block contributes fields 0 .. rem - 1
-  if (nadv >= 1) {
-    step(x, ctab, force, SgprBarrier());
-    if (TRACE) put_trace(tr + nadv * 9, x);
-    if (rem) {
-      to_ranlux(x, d, force);
-#pragma unroll
-      for (int f = 0; f < 12; ++f)
-        if ((uint32_t)f < rem) put<F64>(row, base + f, d, f);
+// Draw `count` values for every record with G = 2^lg lanes per record.
+//
+// Block t of a record is the t-th LCG state visited (t = 0 is the state on
+// entry, t = nadv the state after the last advance); the value with output
+// index j is field (pos + j) mod 12 of block (pos + j) / 12.  Lane l of a
+// record starts at block l (X_l = A^l X_0) and then
+// takes blocks l + G, l + 2G, ... using the folded multiplier of A^G (ctabs
+// holds the folded multipliers of A^(2^g), g < 13), so the
+// G lanes of a record hold G consecutive blocks at every iteration.
+//
+// Staged (G > 1): the gs = 2^LGS = min(G, 64) lanes of a record inside one
+// wave write their blocks to LDS and then store them back as consecutive
+// 8-byte values, so each store instruction writes contiguous runs of the
+// output row instead of one value per row per lane.  LGS = 0 is G = 1 (no
+// staging).
+//
+// The record is advanced eagerly: the lane holding block nadv writes it back
+// with pos = (pos + count) mod 12.
+template <bool F64, bool TRACE, int LGS>
+__global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, uint64_t n,
+                                                    uint64_t count, uint64_t* __restrict__ out,
+                                                    uint64_t* __restrict__ trace, uint64_t trace_steps,
+                                                    const uint32_t* __restrict__ ctabs, uint32_t lg,
+                                                    uint32_t p, uint32_t* __restrict__ err,
+                                                    int force_general) {
+  constexpr bool STAGED = LGS > 0;
+  constexpr uint32_t gs = 1u << LGS;  // lanes of a record inside one wave
+  __shared__ uint64_t stage[STAGED ? BLOCK * FIELDS : 1];
+  const uint32_t tid_blk = threadIdx.x;
+  const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + tid_blk;
+  const uint64_t G = 1ull << lg;
+  const uint64_t i = tid >> lg;
+  const uint32_t l = (uint32_t)(tid & (G - 1));
+  const bool force = force_general != 0;
+
+  uint32_t x[NW];
+  uint32_t pos = 0, sp = 0;
+  bool active = i < n;
+  if (active) {
+    load_record(st, i, x, pos, sp);
+    const uint32_t bad = check_record(x, pos, sp, p);
+    if (bad) {
+      if (l == 0) atomicOr(err, bad);
+      active = false;
     }
   }
-  store_record(st, i, x, rem, sp);
+  if (!active) {
+    set_one(x);
+    pos = 0;
+  }
+  const uint64_t total = pos + count;
+  const uint64_t nadv = total / FIELDS;
+  const uint32_t rem = (uint32_t)(total % FIELDS);
+
+  // lane l starts at block l: X_l = A^l X_0, one folded step by A^(2^b) for
+  // every set bit b of l (bits 6 and up are the same for the whole wave)
+  if (STAGED) {
+#pragma unroll 1
+    for (uint32_t b = 0; b < lg; ++b) {
+      const bool set = ((l >> b) & 1u) != 0;
+      if (__any(set) && set) step(x, ctabs + (size_t)b * NL * NW, force, SgprBarrier());
+    }
+  }
+  const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * NL * NW;
+
+  uint64_t* row = out + i * count;
+  uint64_t* tr = TRACE ? trace + i * trace_steps * 9 : nullptr;
+  const uint32_t ls = l & (gs - 1);
+  uint32_t d[NW];
+
+  for (uint64_t k = 0;; ++k) {
+    const uint64_t t = l + (k << lg);
+    const bool live = active && t <= nadv;
+    if (!__any(live)) break;
+    if (live) {
+      if (TRACE) put_trace(tr + t * 9, x);
+      if (t == nadv) store_record(st, i, x, rem, sp);
+    }
+    to_ranlux(x, d, force);
+    if (!STAGED) {
+      if (live) {
+        const int64_t jb = (int64_t)(t * FIELDS) - (int64_t)pos;
+#pragma unroll
+        for (int f = 0; f < FIELDS; ++f) {
+          const int64_t j = jb + f;
+          if (j >= 0 && (uint64_t)j < count) row[j] = field_bits<F64>(d, f);
+        }
+      }
+    } else {
+      uint64_t* mine = stage + (size_t)tid_blk * FIELDS;
+#pragma unroll
+      for (int f = 0; f < FIELDS; ++f) mine[f] = field_bits<F64>(d, f);
+      wave_sync();
+      // the group's blocks t - ls .. t - ls + gs - 1 are stage entries
+      // [0, 12 gs) in output order; lane ls stores entries q gs + ls
+      const uint64_t* grp = stage + (size_t)(tid_blk - ls) * FIELDS + ls;
+      const int64_t jb = (int64_t)((t - ls) * FIELDS) - (int64_t)pos;
+      if (active) {
+        if (jb >= 0 && (uint64_t)jb + FIELDS * gs <= count) {
+          // the group's whole range lies inside the row
+          uint64_t* dst = row + jb + ls;
+#pragma unroll
+          for (int q = 0; q < FIELDS; ++q) dst[q * gs] = grp[q * gs];
+        } else {
+#pragma unroll
+          for (int q = 0; q < FIELDS; ++q) {
+            const int64_t j = jb + q * gs + ls;
+            if (j >= 0 && (uint64_t)j < count) row[j] = grp[q * gs];
+          }
+        }
+      }
+      wave_sync();
+    }
+    if (__any(live && t + G <= nadv)) step(x, ctab, force, SgprBarrier());
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -437,7 +511,7 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
   k_tab_base<<<1, 64, 0, s>>>(t.T, p);
   const int fill = TAB_ROWS * (TAB_COLS - 2);
   k_tab_fill<<<(fill + 63) / 64, 64, 0, s>>>(t.T);
-  k_tab_fold<<<1, 64, 0, s>>>(t.T, t.C);
+  k_tab_fold<<<FOLD_G, 64, 0, s>>>(t.T, t.C);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     (void)hipFree(t.T);
     (void)hipFree(t.C);
@@ -446,6 +520,25 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
   g_tables[key] = t;
   *out = t;
   return RLX_OK;
+}
+
+std::atomic<uint32_t> g_lanes_override{0};
+
+// Lanes per record: the largest power of two G <= 4096 such that the launch
+// stays within about eight waves per SIMD (2^19 lanes on 256 CUs) and every
+// lane still takes at least 24 generator steps, which keeps the per-lane
+// start-up (up to three generic multiplications) small.
+uint32_t auto_lanes(uint64_t n, uint64_t count) {
+  const uint64_t steps = count / FIELDS + 1;
+  const uint64_t target = 1ull << 19;
+  uint64_t g = 1;
+  while (g < 4096 && n <= target / (g * 2) && steps / (g * 2) >= 24) g *= 2;
+  return (uint32_t)g;
+}
+
+uint32_t lanes_for(uint64_t n, uint64_t count) {
+  const uint32_t o = g_lanes_override.load(std::memory_order_relaxed);
+  return o ? o : auto_lanes(n, count);
 }
 
 template <bool F64, bool TRACE>
@@ -461,8 +554,11 @@ int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint
     const uint64_t need = (11 + count) / 12 + 1;
     if (trace_steps < need || trace_steps > UINT64_MAX / 72 / n) return RLX_EINVAL;
   }
+  const uint32_t G = lanes_for(n, count);
+  const uint32_t lg = (uint32_t)__builtin_ctz(G);
+  if (n > (UINT64_MAX >> lg)) return RLX_EINVAL;
   dim3 grid;
-  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  if (!grid_for(n << lg, &grid)) return RLX_EINVAL;
   hipStream_t s = as_stream(stream);
   Tables t;
   int rc = tables(p, s, &t);
@@ -470,8 +566,17 @@ int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint
   uint32_t* err;
   rc = error_word(s, &err);
   if (rc) return rc;
-  k_generate<F64, TRACE><<<grid, BLOCK, 0, s>>>(states, n, count, out, trace, trace_steps, t.C, p, err,
-                                                force_general);
+  uint64_t* o = reinterpret_cast<uint64_t*>(out);
+  const uint32_t lgs = lg < 6 ? lg : 6;
+#define RLX_GEN(L)                                                                                    \
+  case L:                                                                                             \
+    k_generate<F64, TRACE, L><<<grid, BLOCK, 0, s>>>(states, n, count, o, trace, trace_steps, t.C, lg, p, \
+                                                     err, force_general);                             \
+    break;
+  switch (lgs) {
+    RLX_GEN(0) RLX_GEN(1) RLX_GEN(2) RLX_GEN(3) RLX_GEN(4) RLX_GEN(5) RLX_GEN(6)
+  }
+#undef RLX_GEN
   return launch_status();
 }
 
@@ -565,6 +670,14 @@ int rlx_test_generate_u64_general(rlx_state* states, uint64_t n, uint64_t count,
                                   uint32_t p, void* stream) {
   return generate_impl<false, false>(states, n, count, out, nullptr, 0, p, stream, 1);
 }
+
+int rlx_set_lanes_per_stream(uint32_t lanes) {
+  if (lanes != 0 && (lanes > 4096 || (lanes & (lanes - 1)) != 0)) return RLX_EINVAL;
+  g_lanes_override.store(lanes, std::memory_order_relaxed);
+  return RLX_OK;
+}
+
+uint32_t rlx_lanes_per_stream(uint64_t n, uint64_t count) { return lanes_for(n, count); }
 
 int rlx_check_errors(void* stream, uint32_t* flags) {
   hipStream_t s = as_stream(stream);

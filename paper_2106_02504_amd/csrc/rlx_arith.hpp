@@ -225,7 +225,7 @@ RLX_HD void unpack27(const uint32_t (&w)[NW], uint32_t (&l)[NL]) {
 // Identity map of a table offset; kernels pass one that hides the offset
 // from the optimiser (see step()).
 struct Plain {
-  RLX_HD uint32_t operator()(uint32_t v) const { return v; }
+  RLX_HD uint32_t operator()(uint32_t v, uint32_t) const { return v; }
 };
 
 // X <- A X mod m.  `tab` holds C_j = A 2^(27 j) mod m, row j = 18 words.
@@ -236,17 +236,35 @@ RLX_HD void step(uint32_t (&x)[NW], const uint32_t* __restrict__ tab, bool force
   uint32_t l[NL];
   unpack27(x, l);
   uint64_t s[NW];
+  // Rows of the table are read with scalar loads one row ahead of the
+  // multiply-adds that use them.  Scalar loads complete out of order, so a
+  // wave can only wait for all of them; the load of row j + 1 must therefore
+  // be issued after the wait for row j and before row j's multiply-adds.  On
+  // the GPU `launder` makes the row offset opaque and ties it to a word of
+  // the previous row, which enforces exactly that order (and keeps the
+  // compiler from hoisting all 396 words into scalar registers at once).
+  uint32_t cur[NW];
+  {
+    const uint32_t* __restrict__ row = tab + launder(0u, 0u);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) cur[k] = row[k];
+  }
 #pragma unroll
   for (int j = 0; j < NL; ++j) {
-    // Row j of the table is read with scalar loads right before its 18
-    // multiply-adds.  On the GPU `launder` makes the row offset opaque, so
-    // the compiler cannot hoist all 396 table words into scalar registers
-    // at once (they do not fit).
-    const uint32_t* __restrict__ row = tab + launder((uint32_t)(j * NW));
+    uint32_t nxt[NW];
+    if (j + 1 < NL) {
+      const uint32_t* __restrict__ row = tab + launder((uint32_t)((j + 1) * NW), cur[0]);
+#pragma unroll
+      for (int k = 0; k < NW; ++k) nxt[k] = row[k];
+    }
 #pragma unroll
     for (int k = 0; k < NW; ++k) {
-      const uint64_t prod = (uint64_t)l[j] * row[k];
+      const uint64_t prod = (uint64_t)l[j] * cur[k];
       s[k] = j == 0 ? prod : s[k] + prod;
+    }
+    if (j + 1 < NL) {
+#pragma unroll
+      for (int k = 0; k < NW; ++k) cur[k] = nxt[k];
     }
   }
   // carry-normalise to 18 words plus the word h above 2^576

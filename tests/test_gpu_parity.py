@@ -338,3 +338,56 @@ def test_skip_workload_sampled():
     recs = tensor_to_records(st[torch.tensor(sample, device=DEV)])
     for i, r in zip(sample, recs):
         assert r == (O.skip(O.seed(i, p), int(offs[i]), p), 0, p)
+
+
+# --- lanes per stream: the values never depend on the launch shape --------------
+
+@pytest.fixture
+def lanes_reset():
+    yield
+    rlx.set_lanes_per_stream(0)
+
+
+@pytest.mark.parametrize("G", (1, 2, 4, 8, 16, 32, 64, 128, 1024, 4096))
+def test_lanes_per_stream_bit_identical(G, lanes_reset):
+    rng = random.Random(200 + G)
+    p = 218
+    n, count = 37, 12 * 70 + 7
+    recs = [(O.seed(i + 3, p), rng.randrange(12), p) for i in range(n)]
+    st = records_to_tensor(recs)
+    rlx.set_lanes_per_stream(G)
+    assert rlx.lanes_per_stream(n, count) == G
+    out = rlx.generate_u64(st, count, p)
+    exp, fin = oracle_draws(recs, count)
+    assert out.cpu().numpy().tolist() == exp
+    assert tensor_to_records(st) == fin
+    # f64 with trace (all records share pos 0 for the trace layout)
+    st2 = records_to_tensor([(O.seed(i + 3, p), 0, p) for i in range(n)])
+    vals, trace = rlx.generate_f64_trace(st2, count, p)
+    u = (vals * 2.0 ** 48).to(torch.int64).cpu().numpy()
+    for i in range(0, n, 5):
+        ex, _, _ = O.draws(O.seed(i + 3, p), 0, p, count)
+        assert u[i].tolist() == ex
+        tr = words_to_ints(trace[i].cpu().numpy())
+        x = O.seed(i + 3, p)
+        for t in range(count // 12 + 1):
+            assert tr[t] == x, (i, t)
+            x = O.mulmod(O.multiplier(p), x)
+
+
+@pytest.mark.parametrize("G", (2, 8, 64, 256))
+def test_lanes_short_counts_and_general_path(G, lanes_reset):
+    # counts shorter than a lane's share, every pos, and the general branch
+    rng = random.Random(300 + G)
+    p = 24
+    recs = [(x, rng.randrange(12), p) for x in crafted_states(rng, 100)]
+    rlx.set_lanes_per_stream(G)
+    for count in (1, 5, 12, 13, 40, 12 * G + 1):
+        st_a = records_to_tensor(recs)
+        st_b = st_a.clone()
+        a = rlx.generate_u64(st_a, count, p)
+        b = rlx.test_generate_u64_general(st_b, count, p)
+        exp, fin = oracle_draws(recs, count)
+        assert a.cpu().numpy().tolist() == exp, count
+        assert torch.equal(a, b) and torch.equal(st_a, st_b)
+        assert tensor_to_records(st_a) == fin
