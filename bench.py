@@ -54,6 +54,35 @@ def _oracle_chunk(args):
     return lo, out
 
 
+def _oracle_windows(args):
+    sid, p, count, windows = args
+    import oracle as O
+    x0 = O.seed(sid, p)
+    return [(w, O.window(x0, p, w, n)) for w, n in windows]
+
+
+def batch_sample(reqs, k=24, width=512):
+    """Requests of the batched workload checked against the oracle: their
+    first and last `width` values."""
+    import random
+    rng = random.Random(44)
+    idx = sorted(set([0, len(reqs) - 1] + rng.sample(range(len(reqs)), k)))
+    out = []
+    for i in idx:
+        r = reqs[i]
+        n = min(r.count, width)
+        wins = [(0, n)] + ([(r.count - n, n)] if r.count > n else [])
+        out.append((i, (r.stream_id, r.p, r.count, wins)))
+    return out
+
+
+def oracle_checks(items, workers: int):
+    ctx = mp.get_context("fork")
+    with ctx.Pool(workers) as pool:
+        res = pool.map(_oracle_windows, [a for _, a in items])
+    return {i: r for (i, _), r in zip(items, res)}
+
+
 def cpu_baseline(n_streams: int, workers: int):
     import numpy as np
     chunk = max(1, n_streams // (workers * 8))
@@ -103,6 +132,68 @@ def timed(fn, stream, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps
 
 
+def batch_leg(rlx, torch, np, dev, reqs, checks, args):
+    """8192 requests (own stream each, p uniform over 5 levels, log-uniform
+    counts in [1, 2^20]) in one persistent launch; lanes per segment and
+    segment length from the autotuner; also replayed from a HIP graph."""
+    from paper_2106_02504_amd import autotune
+    n = len(reqs)
+    st = rlx.new_states(n, device=dev)
+    by_p = {}
+    for r in reqs:
+        by_p.setdefault(r.p, []).append(r.stream_id)
+    for p, ids in by_p.items():
+        sub = rlx.new_states(len(ids), device=dev)
+        rlx.init_streams(sub, p, ids=torch.tensor(ids, dtype=torch.int64, device=dev))
+        st[torch.tensor(ids, device=dev)] = sub
+    req = rlx.requests_array([r.stream_id for r in reqs], 0, [r.count for r in reqs], [r.p for r in reqs])
+    total = int(req["count"].sum())
+    out = torch.empty(total, dtype=torch.float64, device=dev)
+    tuned = autotune.tune(req, st, out)
+    plan = rlx.Plan(req, lanes=tuned["lanes"], seg_blocks=tuned["seg_blocks"], device=dev)
+    reps = max(5, args.steps // 2)
+    ms = autotune.time_plan(plan, st, out, reps)
+    # the same launch replayed from a HIP graph
+    s = torch.cuda.Stream(device=dev)
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        plan.generate_f64(st, out)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        plan.generate_f64(st, out)
+    g.replay()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    e1.synchronize()
+    gms = e0.elapsed_time(e1) / reps
+    exact = None
+    if checks is not None:
+        exact = True
+        for i, wins in checks.items():
+            o = int(req["out_offset"][i])
+            for w, vals in wins:
+                got = (out[o + w:o + w + len(vals)] * 2.0 ** 48).to(torch.int64).cpu().numpy()
+                exact &= got.view(np.uint64).tolist() == vals
+    info = plan.info()
+    plan.close()
+    return {"value": total / (ms * 1e-3), "unit": "doubles/s", "ms_per_launch": ms,
+            "graph_replay_ms": gms, "graph_value": total / (gms * 1e-3),
+            "lanes_per_segment": tuned["lanes"], "seg_blocks": tuned["seg_blocks"],
+            "draws_per_lane": 12 * tuned["seg_blocks"] // tuned["lanes"],
+            "autotune": {"cached": tuned.get("cached"), "table": tuned.get("table")},
+            "requests": n, "values": total, "segments": info["segments"], "items": info["items"],
+            "bit_exact_sample": exact,
+            "workload": "8192 requests, own stream each (id r), p uniform over {24,218,404,794,2048}, "
+                        "counts floor(2^(20U)) in [1, 2^20], one persistent launch"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,7 +201,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=8192)
-    ap.add_argument("--legs", default="u64,single,skip", help="extra legs to time (comma list or 'none')")
+    ap.add_argument("--legs", default="u64,single,skip,batch", help="extra legs to time (comma list or 'none')")
     ap.add_argument("--lanes", type=int, default=0, help="force lanes per stream (0 = library's pick)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -122,8 +213,14 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
+    import workloads
+    wanted = set() if args.legs == "none" else set(args.legs.split(","))
+    batch_reqs = workloads.batch_requests() if "batch" in wanted else None
     cpu = None
+    checks = None
     if not args.no_cpu:
+        if batch_reqs is not None:
+            checks = oracle_checks(batch_sample(batch_reqs), min(16, os.cpu_count() or 1))
         workers = min(16, os.cpu_count() or 1)
         ref, cpu_dt = cpu_baseline(args.cpu_streams, workers)
         cpu = {"value": args.cpu_streams * DRAWS / cpu_dt, "unit": "doubles/s", "cores": workers,
@@ -191,7 +288,6 @@ def main() -> int:
                             "against one full-rate 32-bit VALU op per lane per cycle"}
 
     legs = {}
-    wanted = set() if args.legs == "none" else set(args.legs.split(","))
     if "u64" in wanted:
         outu = torch.empty((N_STREAMS, DRAWS), dtype=torch.int64, device=dev)
 
@@ -225,6 +321,10 @@ def main() -> int:
         legs["skip"] = {"value": n3 / dt, "unit": "states/s", "ms_per_step": dt * 1e3,
                         "workload": "2^20 states, offsets log-uniform in [1, 2^64) steps"}
         del st3, offs
+
+    if "batch" in wanted:
+        del out
+        legs["batch"] = batch_leg(rlx, torch, np, dev, batch_reqs, checks, args)
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB

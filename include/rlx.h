@@ -140,6 +140,65 @@ int rlx_generate_f64_trace(rlx_state *states, uint64_t n, uint64_t count,
 int rlx_set_lanes_per_stream(uint32_t lanes);
 uint32_t rlx_lanes_per_stream(uint64_t n, uint64_t count);
 
+/* ---- batched generation ---------------------------------------------------
+ * Many requests, each a window of one stream, in ONE persistent launch that
+ * fuses skip-ahead, generation and conversion.  A request reads its stream
+ * record without modifying it, so several requests may read the same record
+ * (e.g. consecutive windows of one stream) and their results are exactly the
+ * values a plain rlx_generate_f64 would produce at those positions. */
+
+/* One request: values start, start + 1, ..., start + count - 1 of the stream
+ * whose current position is record `state` (position 0 = the record's next
+ * value), written to out[out_offset .. out_offset + count).  p must be the
+ * record's luxury level. */
+typedef struct rlx_request {
+    uint64_t state;       /* index into the states array */
+    uint64_t start;       /* first value, counted from the record's position */
+    uint64_t count;       /* number of values */
+    uint64_t out_offset;  /* element offset in the output array */
+    uint32_t p;           /* luxury level */
+    uint32_t reserved;    /* must be 0 */
+} rlx_request;
+
+/* A plan holds the device descriptors of a batch (library-owned device
+ * memory).  The planner splits every request into segments of at most
+ * `seg_blocks` generator steps, gives each segment `lanes` (a power of two <=
+ * 64) lanes that interleave its steps, and groups segments of one luxury
+ * level into work items of 64 lanes.  At most 16 distinct luxury levels per
+ * plan. */
+typedef struct rlx_plan rlx_plan;
+
+/* Create a plan for n host requests (capacity for later updates is sized
+ * for `capacity_segments` segments; 0 = exactly what these requests need).
+ * Builds the tables of every luxury level used (synchronising `stream`
+ * once per new level) and uploads the descriptors on `stream`. */
+int rlx_plan_create(rlx_plan **plan, const rlx_request *reqs, uint64_t n,
+                    uint32_t lanes, uint64_t seg_blocks,
+                    uint64_t capacity_segments, void *stream);
+
+/* Re-plan new requests into an existing plan's device buffers (same lanes and
+ * seg_blocks) with an asynchronous upload on `stream`; RLX_EINVAL if they
+ * need more segments than the plan's capacity.  The buffers keep their
+ * addresses, so a HIP graph that captured rlx_plan_generate_* replays the
+ * new requests. */
+int rlx_plan_update(rlx_plan *plan, const rlx_request *reqs, uint64_t n, void *stream);
+
+/* Number of segments and work items of the plan's current requests. */
+int rlx_plan_info(const rlx_plan *plan, uint64_t *segments, uint64_t *items,
+                  uint64_t *total_values);
+
+/* Run the plan: one counter-reset kernel and one persistent kernel on
+ * `stream` (no allocation, no synchronisation, no memset: capturable).
+ * The launch reads the work list, its length and the luxury tables from the
+ * plan's device memory, so a captured launch runs whatever requests the plan
+ * holds when it is replayed.  `states` are read only.  out must hold every
+ * request's range. */
+int rlx_plan_generate_f64(rlx_plan *plan, const rlx_state *states, double *out, void *stream);
+int rlx_plan_generate_u64(rlx_plan *plan, const rlx_state *states, uint64_t *out, void *stream);
+
+/* Free the plan (synchronises the device first). */
+int rlx_plan_destroy(rlx_plan *plan);
+
 /* Synchronise `stream`, then read and clear the device error word of the
  * current device: *flags receives the RLX_ERR_* bits set by kernels since
  * the last call.  Returns RLX_ESTATE if any bit was set. */

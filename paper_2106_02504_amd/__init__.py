@@ -25,7 +25,7 @@ import torch  # load torch's HIP runtime first: librlx.so binds to the same one
 __all__ = [
     "RlxError", "lib", "new_states", "prepare", "init_streams", "skip",
     "generate_f64", "generate_u64", "generate_f64_trace", "check_errors",
-    "set_lanes_per_stream", "lanes_per_stream",
+    "set_lanes_per_stream", "lanes_per_stream", "REQUEST_DTYPE", "requests_array", "Plan",
     "constants", "test_mulmod", "test_pow", "test_to_ranlux",
     "test_generate_u64_general", "STATE_WORDS",
 ]
@@ -52,6 +52,12 @@ _SIGS = {
     "rlx_set_lanes_per_stream": (_int, [_u32]),
     "rlx_lanes_per_stream": (_u32, [_u64, _u64]),
     "rlx_constants": (None, [ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
+    "rlx_plan_create": (_int, [ctypes.POINTER(_vp), _vp, _u64, _u32, _u64, _u64, _vp]),
+    "rlx_plan_update": (_int, [_vp, _vp, _u64, _vp]),
+    "rlx_plan_info": (_int, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
+    "rlx_plan_generate_f64": (_int, [_vp, _vp, _vp, _vp]),
+    "rlx_plan_generate_u64": (_int, [_vp, _vp, _vp, _vp]),
+    "rlx_plan_destroy": (_int, [_vp]),
     "rlx_test_mulmod": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "rlx_test_pow": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "rlx_test_to_ranlux": (_int, [_vp, _vp, _vp, _u64, _vp]),
@@ -59,6 +65,13 @@ _SIGS = {
 }
 
 _lib = None
+
+# struct rlx_request: state, start, count, out_offset (uint64), p, reserved (uint32)
+import numpy as _np  # noqa: E402
+
+REQUEST_DTYPE = _np.dtype([("state", "<u8"), ("start", "<u8"), ("count", "<u8"),
+                           ("out_offset", "<u8"), ("p", "<u4"), ("reserved", "<u4")])
+assert REQUEST_DTYPE.itemsize == 40
 
 
 class RlxError(RuntimeError):
@@ -193,6 +206,84 @@ def set_lanes_per_stream(lanes: int) -> None:
 def lanes_per_stream(n: int, count: int) -> int:
     """The G a generate call with n records and `count` values would use."""
     return int(lib().rlx_lanes_per_stream(n, count))
+
+
+def requests_array(state, start, count, p, out_offset=None) -> "_np.ndarray":
+    """Build a host array of rlx_request from per-request sequences; output
+    offsets default to the prefix sums of the counts."""
+    state = _np.asarray(state, dtype=_np.uint64)
+    n = state.shape[0]
+    a = _np.zeros(n, dtype=REQUEST_DTYPE)
+    a["state"] = state
+    a["start"] = _np.broadcast_to(_np.asarray(start, dtype=_np.uint64), (n,))
+    a["count"] = _np.asarray(count, dtype=_np.uint64)
+    a["p"] = _np.broadcast_to(_np.asarray(p, dtype=_np.uint32), (n,))
+    if out_offset is None:
+        off = _np.zeros(n, dtype=_np.uint64)
+        if n > 1:
+            off[1:] = _np.cumsum(a["count"][:-1], dtype=_np.uint64)
+        a["out_offset"] = off
+    else:
+        a["out_offset"] = _np.asarray(out_offset, dtype=_np.uint64)
+    return a
+
+
+class Plan:
+    """A batch of requests planned for the persistent kernel (rlx_plan_*).
+
+    `requests` is a host array of REQUEST_DTYPE.  lanes: lanes per segment
+    (power of two <= 64); seg_blocks: maximum generator steps per segment.
+    """
+
+    def __init__(self, requests, lanes: int = 8, seg_blocks: int = 2048, capacity_segments: int = 0,
+                 device: torch.device | str | None = None):
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        req = _np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
+        self._h = _vp()
+        with torch.cuda.device(self.device):
+            _check(lib().rlx_plan_create(ctypes.byref(self._h), req.ctypes.data, req.shape[0], lanes, seg_blocks,
+                                         capacity_segments, _stream()), "rlx_plan_create")
+        self.lanes, self.seg_blocks = lanes, seg_blocks
+
+    def update(self, requests) -> None:
+        req = _np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
+        with torch.cuda.device(self.device):
+            _check(lib().rlx_plan_update(self._h, req.ctypes.data, req.shape[0], _stream()), "rlx_plan_update")
+
+    def info(self) -> dict:
+        a, b, c = _u64(0), _u64(0), _u64(0)
+        _check(lib().rlx_plan_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)), "rlx_plan_info")
+        return {"segments": a.value, "items": b.value, "values": c.value}
+
+    def generate_f64(self, states: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        _need_states(states)
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.device != states.device:
+            raise ValueError("out must be a contiguous float64 tensor on the states' device")
+        with torch.cuda.device(states.device):
+            _check(lib().rlx_plan_generate_f64(self._h, states.data_ptr(), out.data_ptr(), _stream()),
+                   "rlx_plan_generate_f64")
+        return out
+
+    def generate_u64(self, states: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        _need_states(states)
+        if out.dtype != torch.int64 or not out.is_contiguous() or out.device != states.device:
+            raise ValueError("out must be a contiguous int64 tensor on the states' device")
+        with torch.cuda.device(states.device):
+            _check(lib().rlx_plan_generate_u64(self._h, states.data_ptr(), out.data_ptr(), _stream()),
+                   "rlx_plan_generate_u64")
+        return out
+
+    def close(self) -> None:
+        if self._h:
+            _check(lib().rlx_plan_destroy(self._h), "rlx_plan_destroy")
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            if self._h:
+                lib().rlx_plan_destroy(self._h)
+        except Exception:
+            pass
 
 
 def check_errors() -> int:

@@ -8,8 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", "rlx.hip")]
-DEPS = SRC + [os.path.join(HERE, "csrc", "rlx_arith.hpp"), os.path.join(ROOT, "include", "rlx.h")]
+SRC = [os.path.join(HERE, "csrc", "rlx.hip"), os.path.join(HERE, "csrc", "rlx_batch.hip")]
 LIB = os.path.join(HERE, "librlx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

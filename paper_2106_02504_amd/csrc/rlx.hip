@@ -4,15 +4,9 @@
 //   k_tab_base / k_tab_fill / k_tab_fold   per-luxury-level constant tables
 //   k_init                                 seeding        (section 2.4)
 //   k_skip                                 skip-ahead     (section 2.4)
-//   k_generate<F64|U64, trace>             draw values    (sections 2.1-2.3)
+//   k_generate<F64|U64, trace, LGS>        draw values    (sections 2.1-2.3)
 //   k_test_*                               generic arithmetic for tests
-//
-// Tables of a luxury level p (device memory owned by the library):
-//   T[i][j] = A_p^(j 16^i) mod m, i < 40, j < 16 (18 words each): 4-bit
-//             windows of a 160-bit exponent; rows 0..15 serve skips of k <
-//             2^64 steps, rows 24..39 serve seeds (exponent 2^96 id).
-//   C[j]    = A_p 2^(27 j) mod m, j < 22: the folded multiplier of the
-//             generator step (see rlx_arith.hpp).
+// The batched persistent kernel and its planner are in rlx_batch.hip.
 #include <hip/hip_runtime.h>
 
 #include <atomic>
@@ -23,98 +17,12 @@
 
 #include "rlx.h"
 #include "rlx_arith.hpp"
+#include "rlx_device.hpp"
+#include "rlx_internal.hpp"
 
 using namespace rlx;
 
 namespace {
-
-constexpr int TAB_ROWS = 40;
-constexpr int TAB_COLS = 16;
-constexpr int SEED_ROW0 = 24;  // 2^96 = 16^24
-constexpr size_t TAB_WORDS = (size_t)TAB_ROWS * TAB_COLS * NW;
-constexpr int FOLD_G = 13;  // lanes per stream G = 2^g, g < 13 (1 .. 4096)
-constexpr size_t FOLD_WORDS = (size_t)FOLD_G * NL * NW;
-constexpr int BLOCK = 256;
-
-// a = 2^576 - 2^552 - 2^240 + 2^216 + 1 = 2^-24 mod m: one subtract-with-
-// borrow step of RANLUX (lags 24 and 10, base 2^24) as an LCG multiplier.
-__device__ __forceinline__ uint32_t a_word(int k) {
-  return k == 0 ? 1u
-       : k < 6  ? 0u
-       : k == 6 ? 0x01000000u
-       : k == 7 ? 0xFFFF0000u
-       : k < 17 ? 0xFFFFFFFFu
-                : 0xFFFFFEFFu;
-}
-
-__device__ __forceinline__ void set_one(uint32_t (&x)[NW]) {
-#pragma unroll
-  for (int k = 0; k < NW; ++k) x[k] = k == 0 ? 1u : 0u;
-}
-
-__device__ __forceinline__ void load_words(const uint32_t* __restrict__ src, uint32_t (&x)[NW]) {
-#pragma unroll
-  for (int k = 0; k < NW; ++k) x[k] = src[k];
-}
-
-__device__ __forceinline__ void store_words(uint32_t* __restrict__ dst, const uint32_t (&x)[NW]) {
-#pragma unroll
-  for (int k = 0; k < NW; ++k) dst[k] = x[k];
-}
-
-__device__ __forceinline__ void copy_words(uint32_t (&dst)[NW], const uint32_t (&src)[NW]) {
-#pragma unroll
-  for (int k = 0; k < NW; ++k) dst[k] = src[k];
-}
-
-// record i: 80 bytes = five 16-byte vectors
-__device__ __forceinline__ void load_record(const rlx_state* __restrict__ st, uint64_t i,
-                                            uint32_t (&x)[NW], uint32_t& pos, uint32_t& p) {
-  const uint4* r = reinterpret_cast<const uint4*>(st + i);
-  uint4 v[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) v[q] = r[q];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    x[4 * q + 0] = v[q].x; x[4 * q + 1] = v[q].y; x[4 * q + 2] = v[q].z; x[4 * q + 3] = v[q].w;
-  }
-  x[16] = v[4].x; x[17] = v[4].y;
-  pos = v[4].z;
-  p = v[4].w;
-}
-
-__device__ __forceinline__ void store_record(rlx_state* __restrict__ st, uint64_t i,
-                                             const uint32_t (&x)[NW], uint32_t pos, uint32_t p) {
-  uint4* r = reinterpret_cast<uint4*>(st + i);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) r[q] = make_uint4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-  r[4] = make_uint4(x[16], x[17], pos, p);
-}
-
-__device__ __forceinline__ uint32_t check_record(const uint32_t (&x)[NW], uint32_t pos, uint32_t sp,
-                                                 uint32_t p) {
-  uint32_t bad = 0;
-  if (sp != p) bad |= RLX_ERR_BAD_P;
-  if (pos > 11) bad |= RLX_ERR_BAD_POS;
-  if (geq_m(x)) bad |= RLX_ERR_BAD_X;
-  return bad;
-}
-
-// Row-offset barrier for the generator step: an empty asm that claims to
-// modify the (scalar) offset using a word `dep` of the previous row, so the
-// table load using the offset cannot move above the arrival of that row.
-struct SgprBarrier {
-  __device__ __forceinline__ uint32_t operator()(uint32_t v, uint32_t dep) const {
-    asm volatile("" : "+s"(v) : "s"(dep));
-    return v;
-  }
-};
-
-__device__ __forceinline__ void mulmod_inplace(uint32_t (&x)[NW], const uint32_t (&y)[NW]) {
-  uint32_t r[NW];
-  mulmod_generic(x, y, r);
-  copy_words(x, r);
-}
 
 // ---------------------------------------------------------------------------
 // tables
@@ -158,7 +66,7 @@ __global__ __launch_bounds__(64) void k_tab_fill(uint32_t* __restrict__ T) {
   store_words(T + ((size_t)i * TAB_COLS + j) * NW, r);
 }
 
-// C_g[j] = A_p^(2^g) 2^(27 j) mod m: block g (g < FOLD_G) builds the folded
+// C_g[j] = A_p^(2^g) 2^(27 j) mod m: block g (g < 64) builds the folded
 // multiplier of a step by 2^g generator steps, one lane per row j.  A_p^(2^g)
 // is a single entry of T: 2^g = v 16^i with v in {1, 2, 4, 8}.
 __global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T, uint32_t* __restrict__ C) {
@@ -171,7 +79,7 @@ __global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T,
 #pragma unroll
   for (int k = 0; k < NW; ++k) pw[k] = (k == (bit >> 5)) ? (1u << (bit & 31)) : 0u;
   mulmod_generic(a, pw, r);
-  store_words(C + ((size_t)g * NL + j) * NW, r);
+  store_words(C + (size_t)g * FOLD_ROW_WORDS + (size_t)j * NW, r);
 }
 
 // ---------------------------------------------------------------------------
@@ -229,47 +137,19 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
 // ---------------------------------------------------------------------------
 // generation (sections 2.1-2.3)
 
-constexpr int FIELDS = 12;
-constexpr int WAVE = 64;
-
-template <bool F64>
-__device__ __forceinline__ uint64_t field_bits(const uint32_t (&d)[NW], int f) {
-  if (F64) {
-    const double v = field_f64(d, f);
-    uint64_t b;
-    __builtin_memcpy(&b, &v, 8);
-    return b;
-  }
-  return field_u64(d, f);
-}
-
-__device__ __forceinline__ void put_trace(uint64_t* __restrict__ tr, const uint32_t (&x)[NW]) {
-#pragma unroll
-  for (int k = 0; k < 9; ++k) tr[k] = ((uint64_t)x[2 * k + 1] << 32) | x[2 * k];
-}
-
-// LDS writes of a wave become visible to the whole wave.
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Draw `count` values for every record with G = 2^lg lanes per record.
 //
 // Block t of a record is the t-th LCG state visited (t = 0 is the state on
 // entry, t = nadv the state after the last advance); the value with output
 // index j is field (pos + j) mod 12 of block (pos + j) / 12.  Lane l of a
-// record starts at block l (X_l = A^l X_0) and then
-// takes blocks l + G, l + 2G, ... using the folded multiplier of A^G (ctabs
-// holds the folded multipliers of A^(2^g), g < 13), so the
-// G lanes of a record hold G consecutive blocks at every iteration.
+// record starts at block l (X_l = A^l X_0, by folded steps) and then takes
+// blocks l + G, l + 2G, ... with the folded multiplier of A^G, so the G lanes
+// of a record hold G consecutive blocks at every iteration.
 //
 // Staged (G > 1): the gs = 2^LGS = min(G, 64) lanes of a record inside one
-// wave write their blocks to LDS and then store them back as consecutive
-// 8-byte values, so each store instruction writes contiguous runs of the
-// output row instead of one value per row per lane.  LGS = 0 is G = 1 (no
-// staging).
+// wave pass their blocks through LDS (stage_store), so each store
+// instruction writes contiguous runs of the output row instead of one value
+// per row per lane.  LGS = 0 is G = 1 (direct stores, no staging).
 //
 // The record is advanced eagerly: the lane holding block nadv writes it back
 // with pos = (pos + count) mod 12.
@@ -309,16 +189,10 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
   const uint64_t nadv = total / FIELDS;
   const uint32_t rem = (uint32_t)(total % FIELDS);
 
-  // lane l starts at block l: X_l = A^l X_0, one folded step by A^(2^b) for
-  // every set bit b of l (bits 6 and up are the same for the whole wave)
-  if (STAGED) {
-#pragma unroll 1
-    for (uint32_t b = 0; b < lg; ++b) {
-      const bool set = ((l >> b) & 1u) != 0;
-      if (__any(set) && set) step(x, ctabs + (size_t)b * NL * NW, force, SgprBarrier());
-    }
-  }
-  const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * NL * NW;
+  // lane l starts at block l: X_l = A^l X_0 (bits 6 and up of l are the
+  // same for the whole wave)
+  if (STAGED) advance(x, l, ctabs, force);
+  const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * FOLD_ROW_WORDS;
 
   uint64_t* row = out + i * count;
   uint64_t* tr = TRACE ? trace + i * trace_steps * 9 : nullptr;
@@ -344,29 +218,10 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
         }
       }
     } else {
-      uint64_t* mine = stage + (size_t)tid_blk * FIELDS;
-#pragma unroll
-      for (int f = 0; f < FIELDS; ++f) mine[f] = field_bits<F64>(d, f);
-      wave_sync();
-      // the group's blocks t - ls .. t - ls + gs - 1 are stage entries
-      // [0, 12 gs) in output order; lane ls stores entries q gs + ls
-      const uint64_t* grp = stage + (size_t)(tid_blk - ls) * FIELDS + ls;
+      // the group's blocks t - ls .. t - ls + gs - 1 hold output indices
+      // from jb on
       const int64_t jb = (int64_t)((t - ls) * FIELDS) - (int64_t)pos;
-      if (active) {
-        if (jb >= 0 && (uint64_t)jb + FIELDS * gs <= count) {
-          // the group's whole range lies inside the row
-          uint64_t* dst = row + jb + ls;
-#pragma unroll
-          for (int q = 0; q < FIELDS; ++q) dst[q * gs] = grp[q * gs];
-        } else {
-#pragma unroll
-          for (int q = 0; q < FIELDS; ++q) {
-            const int64_t j = jb + q * gs + ls;
-            if (j >= 0 && (uint64_t)j < count) row[j] = grp[q * gs];
-          }
-        }
-      }
-      wave_sync();
+      stage_store<F64, LGS>(d, stage, tid_blk, ls, jb, 0, (int64_t)count, active, row);
     }
     if (__any(live && t + G <= nadv)) step(x, ctab, force, SgprBarrier());
   }
@@ -442,25 +297,9 @@ __global__ __launch_bounds__(BLOCK) void k_test_to_ranlux(const uint64_t* __rest
 
 namespace {
 
-struct Tables {
-  uint32_t* T = nullptr;  // TAB_WORDS
-  uint32_t* C = nullptr;  // FOLD_WORDS
-};
-
 std::mutex g_mu;
-std::map<std::pair<int, uint32_t>, Tables> g_tables;
+std::map<std::pair<int, uint32_t>, host::Tables> g_tables;
 std::map<int, uint32_t*> g_err;
-
-inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
-inline bool aligned(const void* ptr, size_t a) { return (reinterpret_cast<uintptr_t>(ptr) % a) == 0; }
-
-inline bool valid_p(uint32_t p) { return p >= 24 && p < (1u << 31); }
-
-inline int launch_status() {
-  hipError_t e = hipGetLastError();
-  return e == hipSuccess ? RLX_OK : RLX_EHIP;
-}
 
 inline bool grid_for(uint64_t n, dim3* g) {
   const uint64_t blocks = (n + BLOCK - 1) / BLOCK;
@@ -471,7 +310,11 @@ inline bool grid_for(uint64_t n, dim3* g) {
 
 int current_device(int* dev) { return hipGetDevice(dev) == hipSuccess ? RLX_OK : RLX_EHIP; }
 
-// device error word of the current device (created zeroed on first use)
+}  // namespace
+
+namespace rlx {
+namespace host {
+
 int error_word(hipStream_t s, uint32_t** out) {
   int dev;
   if (current_device(&dev)) return RLX_EHIP;
@@ -522,12 +365,19 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
   return RLX_OK;
 }
 
+}  // namespace host
+}  // namespace rlx
+
+using namespace rlx::host;
+
+namespace {
+
 std::atomic<uint32_t> g_lanes_override{0};
 
 // Lanes per record: the largest power of two G <= 4096 such that the launch
 // stays within about eight waves per SIMD (2^19 lanes on 256 CUs) and every
 // lane still takes at least 24 generator steps, which keeps the per-lane
-// start-up (up to three generic multiplications) small.
+// start-up (one folded step per set bit of the lane index) small.
 uint32_t auto_lanes(uint64_t n, uint64_t count) {
   const uint64_t steps = count / FIELDS + 1;
   const uint64_t target = 1ull << 19;

@@ -1,0 +1,366 @@
+// rlx_batch.hip -- batched generation: planner and persistent kernel.
+//
+// A batch is a list of requests, each a window [start, start + count) of one
+// stream (values counted from field 0 of the record's current step).  The
+// planner (host) cuts every request into segments of at most `seg_blocks`
+// generator steps and groups segments of the same luxury level into work
+// items of 64 lanes (64 / G segments of G lanes each).  One persistent
+// kernel then pops items from a device counter; inside an item every segment
+// is run by G lanes exactly as the plain kernel runs a record: lane l starts
+// at the segment's block l (skip by folded steps of A^(2^g), section 2.4),
+// then takes every G-th block with the multiplier A^G, converts (section
+// 2.3) and stores through LDS.  Records are only read.
+//
+// Segments are sorted by length (longest first) inside a level and items by
+// cost, so waves that pop late get short items (longest-processing-time
+// order); long requests are cut so that no item dominates the launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "rlx.h"
+#include "rlx_arith.hpp"
+#include "rlx_device.hpp"
+#include "rlx_internal.hpp"
+
+using namespace rlx;
+using namespace rlx::host;
+
+namespace {
+
+constexpr int MAX_LEVELS = 16;
+
+// One segment: blocks block .. block + nblocks - 1 of record `state` (block 0
+// is the record's current LCG state); field f of block block + t has output
+// index jbase + 12 t + f and is written when that index is in [lo, hi).
+struct Segment {
+  uint64_t state;
+  uint64_t block;
+  int64_t jbase;
+  int64_t lo;
+  int64_t hi;
+  uint32_t nblocks;
+  uint32_t slot;  // luxury-level slot
+};
+static_assert(sizeof(Segment) == 48, "segment descriptor layout");
+
+// Work item: segments seg0 .. seg0 + nseg - 1, all of level `slot`.
+struct Item {
+  uint32_t seg0;
+  uint32_t nseg;
+  uint32_t slot;
+  uint32_t cost;  // longest segment, in blocks
+};
+static_assert(sizeof(Item) == 16, "item descriptor layout");
+
+// Device-side header of a plan.  Everything a launch depends on that can
+// change between updates lives here (not in kernel arguments), so a launch
+// captured in a HIP graph replays whatever the plan holds at replay time.
+struct Header {
+  uint32_t counter;  // next work item (reset before every launch)
+  uint32_t n_items;
+  uint32_t pad[2];
+  const uint32_t* C[MAX_LEVELS];  // folded multipliers A^(2^g) of each level
+  uint32_t p[MAX_LEVELS];
+};
+
+__global__ void k_reset(Header* __restrict__ hdr) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->counter = 0;
+}
+
+template <bool F64, int LGS>
+__global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ st,
+                                                 const Segment* __restrict__ segs,
+                                                 const Item* __restrict__ items, Header* __restrict__ hdr,
+                                                 uint64_t* __restrict__ out, uint32_t* __restrict__ err) {
+  constexpr uint32_t G = 1u << LGS;
+  __shared__ uint64_t stage[BLOCK * FIELDS];
+  const uint32_t tid_blk = threadIdx.x;
+  const uint32_t lane = tid_blk & (WAVE - 1);
+  const uint32_t team = lane >> LGS;
+  const uint32_t l = lane & (G - 1);
+  const uint32_t n_items = __builtin_amdgcn_readfirstlane(hdr->n_items);
+  for (;;) {
+    uint32_t it = 0;
+    if (lane == 0) it = atomicAdd(&hdr->counter, 1u);
+    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+    if (it >= n_items) break;
+    const Item item = items[it];
+    const uint32_t slot = __builtin_amdgcn_readfirstlane(item.slot);
+    const uint32_t* __restrict__ ctabs = hdr->C[slot];
+    const uint32_t p = __builtin_amdgcn_readfirstlane(hdr->p[slot]);
+    bool active = team < item.nseg;
+    Segment sg{};
+    uint32_t x[NW];
+    if (active) {
+      sg = segs[item.seg0 + team];
+      uint32_t pos, sp;
+      load_record(st, sg.state, x, pos, sp);
+      uint32_t bad = 0;
+      if (sp != p) bad |= RLX_ERR_BAD_P;
+      if (geq_m(x)) bad |= RLX_ERR_BAD_X;
+      if (bad) {
+        if (l == 0) atomicOr(err, bad);
+        active = false;
+      }
+    }
+    if (!active) {
+      set_one(x);
+      sg.nblocks = 0;
+    }
+    // this lane's first block: sg.block + l
+    advance(x, active ? sg.block + l : 0, ctabs, false);
+    const uint32_t* __restrict__ ctab = ctabs + (size_t)LGS * FOLD_ROW_WORDS;
+    const int64_t lo = sg.lo > sg.jbase ? sg.lo : sg.jbase;
+    const int64_t end = sg.jbase + (int64_t)FIELDS * sg.nblocks;
+    const int64_t hi = sg.hi < end ? sg.hi : end;
+    uint32_t d[NW];
+    for (uint32_t k = 0;; ++k) {
+      const uint32_t t = l + (k << LGS);
+      const bool live = active && t < sg.nblocks;
+      if (!__any(live)) break;
+      to_ranlux(x, d, false);
+      const int64_t jb = sg.jbase + (int64_t)FIELDS * (t - l);
+      stage_store<F64, LGS>(d, stage, tid_blk, l, jb, lo, hi, active, out);
+      if (__any(live && t + G < sg.nblocks)) step(x, ctab, false, SgprBarrier());
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host: the plan
+
+struct rlx_plan {
+  int device = 0;
+  uint32_t lanes = 0, lg = 0;
+  uint64_t seg_blocks = 0;
+  uint64_t cap = 0;  // segments (and items) the device buffers hold
+  Segment* d_segs = nullptr;
+  Item* d_items = nullptr;
+  Header* d_hdr = nullptr;
+  Segment* h_segs = nullptr;  // pinned staging for uploads
+  Item* h_items = nullptr;
+  Header* h_hdr = nullptr;
+  hipEvent_t uploaded = nullptr;
+  uint64_t n_segs = 0, n_items = 0, total = 0;
+};
+
+namespace {
+
+struct Planned {
+  std::vector<Segment> segs;
+  std::vector<Item> items;
+  std::vector<uint32_t> ps;  // luxury level of each slot
+  uint64_t total = 0;
+};
+
+int plan_requests(const rlx_request* reqs, uint64_t n, uint32_t lg, uint64_t seg_blocks, Planned* out) {
+  Planned pl;
+  for (uint64_t r = 0; r < n; ++r) {
+    const rlx_request& q = reqs[r];
+    if (q.reserved != 0 || !valid_p(q.p)) return RLX_EINVAL;
+    if (q.count == 0) continue;
+    if (q.start > UINT64_MAX - q.count) return RLX_EINVAL;
+    if (q.out_offset > (uint64_t)INT64_MAX / 2 || q.count > (uint64_t)INT64_MAX / 2) return RLX_EINVAL;
+    uint32_t slot = 0;
+    while (slot < pl.ps.size() && pl.ps[slot] != q.p) ++slot;
+    if (slot == pl.ps.size()) {
+      if (pl.ps.size() == MAX_LEVELS) return RLX_EINVAL;
+      pl.ps.push_back(q.p);
+    }
+    const uint64_t b0 = q.start / FIELDS;
+    const uint64_t f0 = q.start % FIELDS;
+    const uint64_t nb = (f0 + q.count + FIELDS - 1) / FIELDS;
+    for (uint64_t k = 0; k * seg_blocks < nb; ++k) {
+      Segment s;
+      s.state = q.state;
+      s.block = b0 + k * seg_blocks;
+      s.jbase = (int64_t)q.out_offset + (int64_t)(FIELDS * k * seg_blocks) - (int64_t)f0;
+      s.lo = (int64_t)q.out_offset;
+      s.hi = (int64_t)(q.out_offset + q.count);
+      s.nblocks = (uint32_t)std::min<uint64_t>(seg_blocks, nb - k * seg_blocks);
+      s.slot = slot;
+      pl.segs.push_back(s);
+    }
+    pl.total += q.count;
+  }
+  if (pl.segs.size() > 0xFFFFFFFFull) return RLX_EINVAL;
+  std::stable_sort(pl.segs.begin(), pl.segs.end(), [](const Segment& a, const Segment& b) {
+    return a.slot != b.slot ? a.slot < b.slot : a.nblocks > b.nblocks;
+  });
+  const uint32_t per_item = WAVE >> lg;  // segments per 64-lane item
+  for (size_t i = 0; i < pl.segs.size();) {
+    Item it;
+    it.seg0 = (uint32_t)i;
+    it.slot = pl.segs[i].slot;
+    it.cost = pl.segs[i].nblocks;
+    uint32_t k = 0;
+    while (k < per_item && i < pl.segs.size() && pl.segs[i].slot == it.slot) {
+      ++k;
+      ++i;
+    }
+    it.nseg = k;
+    pl.items.push_back(it);
+  }
+  std::stable_sort(pl.items.begin(), pl.items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  *out = std::move(pl);
+  return RLX_OK;
+}
+
+int upload(rlx_plan* plan, const Planned& pl, hipStream_t s) {
+  if (pl.segs.size() > plan->cap || pl.items.size() > plan->cap) return RLX_EINVAL;
+  if (pl.ps.size() > MAX_LEVELS) return RLX_EINVAL;
+  Header hd{};
+  hd.n_items = (uint32_t)pl.items.size();
+  for (size_t k = 0; k < pl.ps.size(); ++k) {
+    Tables t;
+    const int rc = tables(pl.ps[k], s, &t);
+    if (rc) return rc;
+    hd.C[k] = t.C;
+    hd.p[k] = pl.ps[k];
+  }
+  // the previous upload must have left the staging buffers
+  if (hipEventSynchronize(plan->uploaded) != hipSuccess) return RLX_EHIP;
+  *plan->h_hdr = hd;
+  if (hipMemcpyAsync(plan->d_hdr, plan->h_hdr, sizeof(Header), hipMemcpyHostToDevice, s) != hipSuccess)
+    return RLX_EHIP;
+  if (!pl.segs.empty()) std::memcpy(plan->h_segs, pl.segs.data(), pl.segs.size() * sizeof(Segment));
+  if (!pl.items.empty()) std::memcpy(plan->h_items, pl.items.data(), pl.items.size() * sizeof(Item));
+  if (!pl.segs.empty() &&
+      hipMemcpyAsync(plan->d_segs, plan->h_segs, pl.segs.size() * sizeof(Segment), hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    return RLX_EHIP;
+  if (!pl.items.empty() &&
+      hipMemcpyAsync(plan->d_items, plan->h_items, pl.items.size() * sizeof(Item), hipMemcpyHostToDevice, s) !=
+          hipSuccess)
+    return RLX_EHIP;
+  if (hipEventRecord(plan->uploaded, s) != hipSuccess) return RLX_EHIP;
+  plan->n_segs = pl.segs.size();
+  plan->n_items = pl.items.size();
+  plan->total = pl.total;
+  return RLX_OK;
+}
+
+void free_plan(rlx_plan* p) {
+  if (!p) return;
+  if (p->d_segs) (void)hipFree(p->d_segs);
+  if (p->d_items) (void)hipFree(p->d_items);
+  if (p->d_hdr) (void)hipFree(p->d_hdr);
+  if (p->h_hdr) (void)hipHostFree(p->h_hdr);
+  if (p->h_segs) (void)hipHostFree(p->h_segs);
+  if (p->h_items) (void)hipHostFree(p->h_items);
+  if (p->uploaded) (void)hipEventDestroy(p->uploaded);
+  delete p;
+}
+
+template <bool F64>
+int plan_launch(rlx_plan* plan, const rlx_state* states, void* out, void* stream) {
+  if (!plan) return RLX_EINVAL;
+  if (!states || !out || !aligned(states, 16) || !aligned(out, 8)) return RLX_EINVAL;
+  hipStream_t s = as_stream(stream);
+  uint32_t* err;
+  int rc = error_word(s, &err);
+  if (rc) return rc;
+  // The grid depends only on the plan's capacity, so a captured launch stays
+  // valid after updates: enough waves to fill the chip (or one per item of a
+  // full plan); waves that find the queue empty exit.
+  const uint64_t blocks = std::min<uint64_t>((plan->cap + 3) / 4, 256ull * 8);
+  k_reset<<<1, 64, 0, s>>>(plan->d_hdr);
+  uint64_t* o = reinterpret_cast<uint64_t*>(out);
+#define RLX_BATCH(L)                                                                                      \
+  case L:                                                                                                 \
+    k_batch<F64, L><<<(unsigned)blocks, BLOCK, 0, s>>>(states, plan->d_segs, plan->d_items, plan->d_hdr, o, \
+                                                       err);                                              \
+    break;
+  switch (plan->lg) {
+    RLX_BATCH(0) RLX_BATCH(1) RLX_BATCH(2) RLX_BATCH(3) RLX_BATCH(4) RLX_BATCH(5) RLX_BATCH(6)
+    default: return RLX_EINVAL;
+  }
+#undef RLX_BATCH
+  return launch_status();
+}
+
+}  // namespace
+
+extern "C" {
+
+int rlx_plan_create(rlx_plan** plan, const rlx_request* reqs, uint64_t n, uint32_t lanes, uint64_t seg_blocks,
+                    uint64_t capacity_segments, void* stream) {
+  if (!plan) return RLX_EINVAL;
+  *plan = nullptr;
+  if (n > 0 && !reqs) return RLX_EINVAL;
+  if (lanes == 0 || lanes > (uint32_t)WAVE || (lanes & (lanes - 1)) != 0) return RLX_EINVAL;
+  if (seg_blocks == 0 || seg_blocks > 0x7FFFFFFFull) return RLX_EINVAL;
+  const uint32_t lg = (uint32_t)__builtin_ctz(lanes);
+  Planned pl;
+  int rc = plan_requests(reqs, n, lg, seg_blocks, &pl);
+  if (rc) return rc;
+  rlx_plan* p = new rlx_plan();
+  if (hipGetDevice(&p->device) != hipSuccess) {
+    free_plan(p);
+    return RLX_EHIP;
+  }
+  p->lanes = lanes;
+  p->lg = lg;
+  p->seg_blocks = seg_blocks;
+  p->cap = std::max<uint64_t>({capacity_segments, (uint64_t)pl.segs.size(), 1});
+  if (hipMalloc(&p->d_segs, p->cap * sizeof(Segment)) != hipSuccess ||
+      hipMalloc(&p->d_items, p->cap * sizeof(Item)) != hipSuccess ||
+      hipMalloc(&p->d_hdr, sizeof(Header)) != hipSuccess ||
+      hipHostMalloc(&p->h_hdr, sizeof(Header), 0) != hipSuccess ||
+      hipHostMalloc(&p->h_segs, p->cap * sizeof(Segment), 0) != hipSuccess ||
+      hipHostMalloc(&p->h_items, p->cap * sizeof(Item), 0) != hipSuccess) {
+    free_plan(p);
+    return RLX_ENOMEM;
+  }
+  if (hipEventCreateWithFlags(&p->uploaded, hipEventDisableTiming) != hipSuccess ||
+      hipEventRecord(p->uploaded, as_stream(stream)) != hipSuccess) {
+    free_plan(p);
+    return RLX_EHIP;
+  }
+  rc = upload(p, pl, as_stream(stream));
+  if (rc) {
+    free_plan(p);
+    return rc;
+  }
+  *plan = p;
+  return RLX_OK;
+}
+
+int rlx_plan_update(rlx_plan* plan, const rlx_request* reqs, uint64_t n, void* stream) {
+  if (!plan || (n > 0 && !reqs)) return RLX_EINVAL;
+  Planned pl;
+  int rc = plan_requests(reqs, n, plan->lg, plan->seg_blocks, &pl);
+  if (rc) return rc;
+  return upload(plan, pl, as_stream(stream));
+}
+
+int rlx_plan_info(const rlx_plan* plan, uint64_t* segments, uint64_t* items, uint64_t* total_values) {
+  if (!plan) return RLX_EINVAL;
+  if (segments) *segments = plan->n_segs;
+  if (items) *items = plan->n_items;
+  if (total_values) *total_values = plan->total;
+  return RLX_OK;
+}
+
+int rlx_plan_generate_f64(rlx_plan* plan, const rlx_state* states, double* out, void* stream) {
+  return plan_launch<true>(plan, states, out, stream);
+}
+
+int rlx_plan_generate_u64(rlx_plan* plan, const rlx_state* states, uint64_t* out, void* stream) {
+  return plan_launch<false>(plan, states, out, stream);
+}
+
+int rlx_plan_destroy(rlx_plan* plan) {
+  if (!plan) return RLX_OK;
+  const bool ok = hipDeviceSynchronize() == hipSuccess;
+  free_plan(plan);
+  return ok ? RLX_OK : RLX_EHIP;
+}
+
+}  // extern "C"
