@@ -37,7 +37,8 @@ DRAWS = 4096
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 VALU_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (full-rate 32-bit ops)
 MADS_PER_DOUBLE = 27              # 18 x 18 32-bit multiply-adds per step / 12 doubles
-KERNEL_SOURCES = ("paper_2106_02504_amd/csrc/rlx.hip", "paper_2106_02504_amd/csrc/rlx_arith.hpp")
+KERNEL_SOURCES = ("paper_2106_02504_amd/csrc/rlx.hip", "paper_2106_02504_amd/csrc/rlx_arith.hpp",
+                  "paper_2106_02504_amd/csrc/rlx_device.hpp")
 
 
 # ---------------------------------------------------------------------------
@@ -194,6 +195,28 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
                         "counts floor(2^(20U)) in [1, 2^20], one persistent launch"}
 
 
+def serve_leg(rlx, torch, np, dev, plain_rate, args):
+    """Poisson arrivals of requests of log-uniform size 10^3..10^8 from a pool
+    of 10^6 streams (p = 2048), at 0.5, 0.8 and 0.95 of the plain kernel's
+    measured rate divided by the mean request size."""
+    import workloads
+    from paper_2106_02504_amd.serve import Server
+    mean_n = workloads.mean_serve_size()
+    srv = Server(pool=workloads.SERVE["pool"], p=P, arena_values=1 << 31, slots=3, lanes=16, seg_blocks=2048,
+                 device=dev)
+    res = {"pool": workloads.SERVE["pool"], "p": P, "arena_values": 1 << 31, "slots": 3,
+           "mean_request": mean_n, "runs": []}
+    for frac in (0.5, 0.8, 0.95):
+        lam = frac * plain_rate / mean_n
+        reqs = workloads.serve_requests(args.serve_requests, lam)
+        st = srv.run([r.arrival_s for r in reqs], [r.stream_id for r in reqs], [r.count for r in reqs])
+        summ = st.summary()
+        summ.pop("starts", None)
+        res["runs"].append(dict(load=frac, rate_per_s=lam, **summ))
+    srv.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,7 +224,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=8192)
-    ap.add_argument("--legs", default="u64,single,skip,batch", help="extra legs to time (comma list or 'none')")
+    ap.add_argument("--legs", default="u64,single,skip,batch,serve", help="extra legs to time (comma list or 'none')")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--lanes", type=int, default=0, help="force lanes per stream (0 = library's pick)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -325,6 +349,9 @@ def main() -> int:
     if "batch" in wanted:
         del out
         legs["batch"] = batch_leg(rlx, torch, np, dev, batch_reqs, checks, args)
+
+    if "serve" in wanted:
+        legs["serve"] = serve_leg(rlx, torch, np, dev, value, args)
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB

@@ -199,6 +199,16 @@ int rlx_plan_generate_u64(rlx_plan *plan, const rlx_state *states, uint64_t *out
 /* Free the plan (synchronises the device first). */
 int rlx_plan_destroy(rlx_plan *plan);
 
+/* Host-only dry run of the planner (no GPU needed): validates the requests
+ * exactly as rlx_plan_create does and reports what a plan would hold.  If
+ * `segments` is not NULL it receives up to max_segments rows of six uint64
+ * (state, first block, output index of field 0 of that block as int64,
+ * lo, hi, nblocks | level slot << 32) in launch order: items in decreasing
+ * cost, segments within an item consecutive. */
+int rlx_plan_dry_run(const rlx_request *reqs, uint64_t n, uint32_t lanes,
+                     uint64_t seg_blocks, uint64_t *n_segments, uint64_t *n_items,
+                     uint64_t *total_values, uint64_t *segments, uint64_t max_segments);
+
 /* Synchronise `stream`, then read and clear the device error word of the
  * current device: *flags receives the RLX_ERR_* bits set by kernels since
  * the last call.  Returns RLX_ESTATE if any bit was set. */

@@ -25,7 +25,7 @@ import torch  # load torch's HIP runtime first: librlx.so binds to the same one
 __all__ = [
     "RlxError", "lib", "new_states", "prepare", "init_streams", "skip",
     "generate_f64", "generate_u64", "generate_f64_trace", "check_errors",
-    "set_lanes_per_stream", "lanes_per_stream", "REQUEST_DTYPE", "requests_array", "Plan",
+    "set_lanes_per_stream", "lanes_per_stream", "REQUEST_DTYPE", "requests_array", "Plan", "plan_dry_run",
     "constants", "test_mulmod", "test_pow", "test_to_ranlux",
     "test_generate_u64_general", "STATE_WORDS",
 ]
@@ -58,6 +58,8 @@ _SIGS = {
     "rlx_plan_generate_f64": (_int, [_vp, _vp, _vp, _vp]),
     "rlx_plan_generate_u64": (_int, [_vp, _vp, _vp, _vp]),
     "rlx_plan_destroy": (_int, [_vp]),
+    "rlx_plan_dry_run": (_int, [_vp, _u64, _u32, _u64, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
+                                ctypes.POINTER(_u64), _vp, _u64]),
     "rlx_test_mulmod": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "rlx_test_pow": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "rlx_test_to_ranlux": (_int, [_vp, _vp, _vp, _u64, _vp]),
@@ -284,6 +286,20 @@ class Plan:
                 lib().rlx_plan_destroy(self._h)
         except Exception:
             pass
+
+
+def plan_dry_run(requests, lanes: int = 8, seg_blocks: int = 2048):
+    """Host-only planner run (no GPU): returns (segments [k, 6] uint64 array
+    in launch order, n_items, total values); see rlx_plan_dry_run."""
+    req = _np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
+    ns, ni, tv = _u64(0), _u64(0), _u64(0)
+    _check(lib().rlx_plan_dry_run(req.ctypes.data, req.shape[0], lanes, seg_blocks, ctypes.byref(ns),
+                                  ctypes.byref(ni), ctypes.byref(tv), None, 0), "rlx_plan_dry_run")
+    segs = _np.zeros((ns.value, 6), dtype=_np.uint64)
+    if ns.value:
+        _check(lib().rlx_plan_dry_run(req.ctypes.data, req.shape[0], lanes, seg_blocks, None, None, None,
+                                      segs.ctypes.data, ns.value), "rlx_plan_dry_run")
+    return segs, ni.value, tv.value
 
 
 def check_errors() -> int:

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
 // of a record hold G consecutive blocks at every iteration.
 //
 // Staged (G > 1): the gs = 2^LGS = min(G, 64) lanes of a record inside one
-// wave pass their blocks through LDS (stage_store), so each store
+// wave pass their blocks through LDS (group_store), so each store
 // instruction writes contiguous runs of the output row instead of one value
 // per row per lane.  LGS = 0 is G = 1 (direct stores, no staging).
 //
@@ -197,7 +197,6 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
   uint64_t* row = out + i * count;
   uint64_t* tr = TRACE ? trace + i * trace_steps * 9 : nullptr;
   const uint32_t ls = l & (gs - 1);
-  uint32_t d[NW];
 
   for (uint64_t k = 0;; ++k) {
     const uint64_t t = l + (k << lg);
@@ -207,8 +206,9 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
       if (TRACE) put_trace(tr + t * 9, x);
       if (t == nadv) store_record(st, i, x, rem, sp);
     }
-    to_ranlux(x, d, force);
     if (!STAGED) {
+      uint32_t d[NW];
+      to_ranlux(x, d, force);
       if (live) {
         const int64_t jb = (int64_t)(t * FIELDS) - (int64_t)pos;
 #pragma unroll
@@ -218,12 +218,13 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
         }
       }
     } else {
+      convert_to_lds<F64>(x, stage + (size_t)tid_blk * FIELDS, force);
       // the group's blocks t - ls .. t - ls + gs - 1 hold output indices
       // from jb on
       const int64_t jb = (int64_t)((t - ls) * FIELDS) - (int64_t)pos;
-      stage_store<F64, LGS>(d, stage, tid_blk, ls, jb, 0, (int64_t)count, active, row);
+      group_store<LGS>(stage, tid_blk, ls, jb, 0, (int64_t)count, active, row);
     }
-    if (__any(live && t + G <= nadv)) step(x, ctab, force, SgprBarrier());
+    if (__any(live && t + G <= nadv)) step(x, constant_table(ctab), force, SgprBarrier());
   }
 }
 

@@ -52,16 +52,20 @@ RLX_HD uint32_t m_word(int k) {
 // ---------------------------------------------------------------------------
 // word helpers
 
+// a + b + c with carry c in {0, 1} (add-with-carry chains)
 RLX_HD uint32_t addc(uint32_t a, uint32_t b, uint32_t& c) {
-  uint64_t s = (uint64_t)a + b + c;
-  c = (uint32_t)(s >> 32);
-  return (uint32_t)s;
+  unsigned int co;
+  const uint32_t r = __builtin_addc(a, b, c, &co);
+  c = co;
+  return r;
 }
 
+// a - b - br with borrow br in {0, 1}
 RLX_HD uint32_t subb(uint32_t a, uint32_t b, uint32_t& br) {
-  uint64_t d = (uint64_t)a - (uint64_t)b - (uint64_t)br;
-  br = (uint32_t)(d >> 63);
-  return (uint32_t)d;
+  unsigned int bo;
+  const uint32_t r = __builtin_subc(a, b, br, &bo);
+  br = bo;
+  return r;
 }
 
 // bits [32 i + s, 32 i + s + 32) of the number w (s in 0..31), reading zeros
@@ -228,11 +232,12 @@ struct Plain {
   RLX_HD uint32_t operator()(uint32_t v, uint32_t) const { return v; }
 };
 
-// X <- A X mod m.  `tab` holds C_j = A 2^(27 j) mod m, row j = 18 words.
-// Returns through `x` the canonical residue.
-template <class Launder = Plain>
-RLX_HD void step(uint32_t (&x)[NW], const uint32_t* __restrict__ tab, bool force_general,
-                 Launder launder = Launder()) {
+// X <- A X mod m.  `tab` holds C_j = A 2^(27 j) mod m, row j = 18 words
+// (kernels pass a pointer into the read-only constant address space, so the
+// rows are fetched with scalar loads).  Returns through `x` the canonical
+// residue.
+template <class Launder = Plain, class TabPtr = const uint32_t*>
+RLX_HD void step(uint32_t (&x)[NW], TabPtr tab, bool force_general, Launder launder = Launder()) {
   uint32_t l[NL];
   unpack27(x, l);
   uint64_t s[NW];
@@ -245,7 +250,7 @@ RLX_HD void step(uint32_t (&x)[NW], const uint32_t* __restrict__ tab, bool force
   // compiler from hoisting all 396 words into scalar registers at once).
   uint32_t cur[NW];
   {
-    const uint32_t* __restrict__ row = tab + launder(0u, 0u);
+    const TabPtr row = tab + launder(0u, 0u);
 #pragma unroll
     for (int k = 0; k < NW; ++k) cur[k] = row[k];
   }
@@ -253,7 +258,7 @@ RLX_HD void step(uint32_t (&x)[NW], const uint32_t* __restrict__ tab, bool force
   for (int j = 0; j < NL; ++j) {
     uint32_t nxt[NW];
     if (j + 1 < NL) {
-      const uint32_t* __restrict__ row = tab + launder((uint32_t)((j + 1) * NW), cur[0]);
+      const TabPtr row = tab + launder((uint32_t)((j + 1) * NW), cur[0]);
 #pragma unroll
       for (int k = 0; k < NW; ++k) nxt[k] = row[k];
     }
@@ -267,29 +272,32 @@ RLX_HD void step(uint32_t (&x)[NW], const uint32_t* __restrict__ tab, bool force
       for (int k = 0; k < NW; ++k) cur[k] = nxt[k];
     }
   }
-  // carry-normalise to 18 words plus the word h above 2^576
+  // carry-normalise to 18 words plus the word h above 2^576.  The carry is
+  // added as c * one + s[k] with an opaque one, which is a single
+  // multiply-add (no zero-extension of c into a register pair).
+  const uint32_t one = launder(1u, 0u);
   uint32_t c = 0;
 #pragma unroll
   for (int k = 0; k < NW; ++k) {
-    uint64_t v = s[k] + c;
+    const uint64_t v = (uint64_t)c * one + s[k];
     x[k] = (uint32_t)v;
     c = (uint32_t)(v >> 32);
   }
   const uint32_t h = c;
-  // fast fold: x - h at words 0-1, x + (h << 16) at words 7-9
+  // fast fold in place: x - h at words 0-1, x + (h << 16) at words 7-9
+  const uint32_t w0 = x[0], w1 = x[1], w7 = x[7], w8 = x[8], w9 = x[9];
   uint32_t br = 0;
-  const uint32_t f0 = subb(x[0], h, br);
-  const uint32_t f1 = subb(x[1], 0u, br);
+  x[0] = subb(w0, h, br);
+  x[1] = subb(w1, 0u, br);
   uint32_t cy = 0;
-  const uint32_t f7 = addc(x[7], h << 16, cy);
-  const uint32_t f8 = addc(x[8], h >> 16, cy);
-  const uint32_t f9 = addc(x[9], 0u, cy);
+  x[7] = addc(w7, h << 16, cy);
+  x[8] = addc(w8, h >> 16, cy);
+  x[9] = addc(w9, 0u, cy);
   // rare: a borrow or carry that runs further, or a result that may be >= m
   const bool rare = (br | cy) != 0 || x[17] == 0xFFFFFFFFu || force_general;
   if (rare) {
+    x[0] = w0; x[1] = w1; x[7] = w7; x[8] = w8; x[9] = w9;
     fold_word_general(x, h);
-  } else {
-    x[0] = f0; x[1] = f1; x[7] = f7; x[8] = f8; x[9] = f9;
   }
 }
 
@@ -333,24 +341,31 @@ RLX_HD void to_ranlux_general(const uint32_t (&x)[NW], uint32_t (&d)[NW]) {
   for (int k = 0; k < NW; ++k) d[k] = subb(d[k], 0u, b2);
 }
 
-RLX_HD void to_ranlux(const uint32_t (&x)[NW], uint32_t (&d)[NW], bool force_general) {
-  // fast path: the carry of X + q0 stops by word 8, the top 32 bits of
-  // D' >> 240 and D' mod 2^336 differ, and subtracting delta does not borrow
-  // past word 0.
+// Fast path of the conversion: writes words 0..8 of D into dlo (words 9..17
+// of D equal those of X) and returns false, or returns true when the general
+// code must be used (rare, or force_general).  The fast path applies when the
+// carry of X + q0 stops by word 8, the top 32 bits of D' >> 240 and D' mod
+// 2^336 differ, and subtracting delta does not borrow past word 0.
+RLX_HD bool to_ranlux_fast(const uint32_t (&x)[NW], uint32_t (&dlo)[9], bool force_general) {
   uint32_t c = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) d[k] = addc(x[k], window32(x, 10 + k, 16), c);
-  d[8] = addc(x[8], 0u, c);
-#pragma unroll
-  for (int k = 9; k < NW; ++k) d[k] = x[k];
+  for (int k = 0; k < 8; ++k) dlo[k] = addc(x[k], window32(x, 10 + k, 16), c);
+  dlo[8] = addc(x[8], 0u, c);
   const uint32_t hi32 = x[17];
   const uint32_t lo32 = window32(x, 9, 16);
   const uint32_t delta = hi32 > lo32 ? 1u : 0u;
-  const bool rare = c != 0 || hi32 == lo32 || (delta != 0 && d[0] == 0) || force_general;
-  if (rare) {
+  const bool rare = c != 0 || hi32 == lo32 || (delta != 0 && dlo[0] == 0) || force_general;
+  dlo[0] -= delta;
+  return rare;
+}
+
+RLX_HD void to_ranlux(const uint32_t (&x)[NW], uint32_t (&d)[NW], bool force_general) {
+  uint32_t dlo[9];
+  if (to_ranlux_fast(x, dlo, force_general)) {
     to_ranlux_general(x, d);
   } else {
-    d[0] -= delta;
+#pragma unroll
+    for (int k = 0; k < NW; ++k) d[k] = k < 9 ? dlo[k] : x[k];
   }
 }
 
@@ -365,36 +380,46 @@ RLX_HD uint32_t ranlux_carry(const uint32_t (&x)[NW], const uint32_t (&d)[NW]) {
 
 // ---------------------------------------------------------------------------
 // 48-bit fields (section 2.3)
+//
+// Field k of D is bits [48k, 48k + 48): with i = k / 2 it lies in words
+// w0 = D[3i], w1 = D[3i + 1], w2 = D[3i + 2] -- the low 48 bits of (w1:w0)
+// for even k, bits 16..63 of (w2:w1) for odd k.
 
-// field k (0..11) of D as (low 32 bits, high 16 bits)
-RLX_HD void field(const uint32_t (&d)[NW], int k, uint32_t& lo, uint32_t& hi) {
-  const int i = k >> 1;
+// funnel shift: bits [s, s + 32) of (hi:lo)
+RLX_HD uint32_t funnel(uint32_t hi, uint32_t lo, int s) {
+  return (uint32_t)((((uint64_t)hi << 32) | lo) >> s);
+}
+
+RLX_HD uint64_t field_u64_w(uint32_t w0, uint32_t w1, uint32_t w2, int k) {
+  if ((k & 1) == 0) return ((uint64_t)(w1 & 0xFFFFu) << 32) | w0;
+  return ((uint64_t)(w2 >> 16) << 32) | funnel(w2, w1, 16);
+}
+
+// v 2^-48 for the 48-bit field v, as the bits of 1 + v 2^-48 (v in the top 48
+// of the 52 mantissa bits) minus 1.0, which is exact.
+RLX_HD double field_f64_w(uint32_t w0, uint32_t w1, uint32_t w2, int k) {
+  uint32_t blo, bhi;
   if ((k & 1) == 0) {
-    lo = d[3 * i];
-    hi = d[3 * i + 1] & 0xFFFFu;
+    blo = w0 << 4;
+    bhi = funnel((w1 & 0xFFFFu) | 0x3FF0000u, w0, 28);
   } else {
-    lo = (d[3 * i + 1] >> 16) | (d[3 * i + 2] << 16);
-    hi = d[3 * i + 2] >> 16;
+    blo = funnel(w2, w1, 12) & 0xFFFFFFF0u;
+    bhi = funnel(0x3FFu, w2, 12);
   }
-}
-
-RLX_HD uint64_t field_u64(const uint32_t (&d)[NW], int k) {
-  uint32_t lo, hi;
-  field(d, k, lo, hi);
-  return ((uint64_t)hi << 32) | lo;
-}
-
-// v 2^-48 for a 48-bit v: 1 + v 2^-48 has v as the top 48 of its 52 mantissa
-// bits; subtracting 1.0 is exact.
-RLX_HD double field_f64(const uint32_t (&d)[NW], int k) {
-  uint32_t lo, hi;
-  field(d, k, lo, hi);
-  const uint32_t bhi = 0x3FF00000u | (hi << 4) | (lo >> 28);
-  const uint32_t blo = lo << 4;
   const uint64_t bits = ((uint64_t)bhi << 32) | blo;
   double one_plus;
   __builtin_memcpy(&one_plus, &bits, 8);
   return one_plus - 1.0;
+}
+
+RLX_HD uint64_t field_u64(const uint32_t (&d)[NW], int k) {
+  const int i = k >> 1;
+  return field_u64_w(d[3 * i], d[3 * i + 1], d[3 * i + 2], k);
+}
+
+RLX_HD double field_f64(const uint32_t (&d)[NW], int k) {
+  const int i = k >> 1;
+  return field_f64_w(d[3 * i], d[3 * i + 1], d[3 * i + 2], k);
 }
 
 }  // namespace rlx

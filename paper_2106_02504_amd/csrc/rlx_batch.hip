@@ -117,15 +117,14 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ s
     const int64_t lo = sg.lo > sg.jbase ? sg.lo : sg.jbase;
     const int64_t end = sg.jbase + (int64_t)FIELDS * sg.nblocks;
     const int64_t hi = sg.hi < end ? sg.hi : end;
-    uint32_t d[NW];
     for (uint32_t k = 0;; ++k) {
       const uint32_t t = l + (k << LGS);
       const bool live = active && t < sg.nblocks;
       if (!__any(live)) break;
-      to_ranlux(x, d, false);
+      convert_to_lds<F64>(x, stage + (size_t)tid_blk * FIELDS, false);
       const int64_t jb = sg.jbase + (int64_t)FIELDS * (t - l);
-      stage_store<F64, LGS>(d, stage, tid_blk, l, jb, lo, hi, active, out);
-      if (__any(live && t + G < sg.nblocks)) step(x, ctab, false, SgprBarrier());
+      group_store<LGS>(stage, tid_blk, l, jb, lo, hi, active, out);
+      if (__any(live && t + G < sg.nblocks)) step(x, constant_table(ctab), false, SgprBarrier());
     }
   }
 }
@@ -354,6 +353,36 @@ int rlx_plan_generate_f64(rlx_plan* plan, const rlx_state* states, double* out, 
 
 int rlx_plan_generate_u64(rlx_plan* plan, const rlx_state* states, uint64_t* out, void* stream) {
   return plan_launch<false>(plan, states, out, stream);
+}
+
+int rlx_plan_dry_run(const rlx_request* reqs, uint64_t n, uint32_t lanes, uint64_t seg_blocks,
+                     uint64_t* n_segments, uint64_t* n_items, uint64_t* total_values, uint64_t* segments,
+                     uint64_t max_segments) {
+  if (n > 0 && !reqs) return RLX_EINVAL;
+  if (lanes == 0 || lanes > (uint32_t)WAVE || (lanes & (lanes - 1)) != 0) return RLX_EINVAL;
+  if (seg_blocks == 0 || seg_blocks > 0x7FFFFFFFull) return RLX_EINVAL;
+  Planned pl;
+  const int rc = plan_requests(reqs, n, (uint32_t)__builtin_ctz(lanes), seg_blocks, &pl);
+  if (rc) return rc;
+  if (n_segments) *n_segments = pl.segs.size();
+  if (n_items) *n_items = pl.items.size();
+  if (total_values) *total_values = pl.total;
+  if (segments) {
+    uint64_t row = 0;
+    for (const Item& it : pl.items) {
+      for (uint32_t k = 0; k < it.nseg && row < max_segments; ++k, ++row) {
+        const Segment& sg = pl.segs[it.seg0 + k];
+        uint64_t* r = segments + 6 * row;
+        r[0] = sg.state;
+        r[1] = sg.block;
+        r[2] = (uint64_t)sg.jbase;
+        r[3] = (uint64_t)sg.lo;
+        r[4] = (uint64_t)sg.hi;
+        r[5] = (uint64_t)sg.nblocks | ((uint64_t)sg.slot << 32);
+      }
+    }
+  }
+  return RLX_OK;
 }
 
 int rlx_plan_destroy(rlx_plan* plan) {

@@ -100,6 +100,16 @@ struct SgprBarrier {
   }
 };
 
+// Table words seen through the constant address space: the compiler may
+// then read them with scalar loads (it treats the memory as unchanging for
+// the whole launch), even when the table address itself was loaded from
+// device memory.
+typedef const __attribute__((address_space(4))) uint32_t const_u32;
+
+__device__ __forceinline__ const_u32* constant_table(const uint32_t* p) {
+  return (const_u32*)p;
+}
+
 __device__ __forceinline__ void mulmod_inplace(uint32_t (&x)[NW], const uint32_t (&y)[NW]) {
   uint32_t r[NW];
   mulmod_generic(x, y, r);
@@ -114,19 +124,57 @@ __device__ __forceinline__ void advance(uint32_t (&x)[NW], uint64_t e, const uin
 #pragma unroll 1
   for (uint32_t g = 0; g < 64 && __any((e >> g) != 0); ++g) {
     const bool set = ((e >> g) & 1u) != 0;
-    if (__any(set) && set) step(x, ctabs + (size_t)g * FOLD_ROW_WORDS, force, SgprBarrier());
+    if (__any(set) && set) step(x, constant_table(ctabs + (size_t)g * FOLD_ROW_WORDS), force, SgprBarrier());
+  }
+}
+
+template <bool F64>
+__device__ __forceinline__ uint64_t field_bits_w(uint32_t w0, uint32_t w1, uint32_t w2, int k) {
+  if (F64) {
+    const double v = field_f64_w(w0, w1, w2, k);
+    uint64_t b;
+    __builtin_memcpy(&b, &v, 8);
+    return b;
+  }
+  return field_u64_w(w0, w1, w2, k);
+}
+
+// Write the 12 fields of one step to this lane's LDS slot.  D's words 0..8
+// are lo[0..8] and words 9..17 are hi[9..17] (after the fast conversion hi is
+// X itself; after the general one both are D).  Per lane, no synchronisation:
+// may run under divergent control flow.
+template <bool F64, int NLO>
+__device__ __forceinline__ void lds_fields(const uint32_t (&lo)[NLO], const uint32_t (&hi)[NW],
+                                           uint64_t* __restrict__ slot) {
+#pragma unroll
+  for (int f = 0; f < FIELDS; f += 2) {
+    const int i = f >> 1;
+    const uint32_t w0 = 3 * i < 9 ? lo[(3 * i) % NLO] : hi[3 * i];
+    const uint32_t w1 = 3 * i + 1 < 9 ? lo[(3 * i + 1) % NLO] : hi[3 * i + 1];
+    const uint32_t w2 = 3 * i + 2 < 9 ? lo[(3 * i + 2) % NLO] : hi[3 * i + 2];
+    slot[f] = field_bits_w<F64>(w0, w1, w2, f);
+    slot[f + 1] = field_bits_w<F64>(w0, w1, w2, f + 1);
+  }
+}
+
+// Convert X (section 2.3) and write its 12 fields to this lane's LDS slot.
+template <bool F64>
+__device__ __forceinline__ void convert_to_lds(const uint32_t (&x)[NW], uint64_t* __restrict__ slot,
+                                               bool force) {
+  uint32_t dlo[9];
+  if (!to_ranlux_fast(x, dlo, force)) {
+    lds_fields<F64>(dlo, x, slot);
+  } else {
+    uint32_t d[NW];
+    to_ranlux_general(x, d);
+    lds_fields<F64>(d, d, slot);
   }
 }
 
 template <bool F64>
 __device__ __forceinline__ uint64_t field_bits(const uint32_t (&d)[NW], int f) {
-  if (F64) {
-    const double v = field_f64(d, f);
-    uint64_t b;
-    __builtin_memcpy(&b, &v, 8);
-    return b;
-  }
-  return field_u64(d, f);
+  const int i = f >> 1;
+  return field_bits_w<F64>(d[3 * i], d[3 * i + 1], d[3 * i + 2], f);
 }
 
 __device__ __forceinline__ void put_trace(uint64_t* __restrict__ tr, const uint32_t (&x)[NW]) {
@@ -141,23 +189,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Store the 12 fields of this lane's block through LDS.
+// Store the 12 fields of this lane's block from LDS.
 //
 // The gs = 2^LGS lanes of a group (gs <= 64, aligned inside the wave) hold
-// consecutive blocks; lane ls holds the group's block ls.  Field f of the
-// group's block m has output index jb + 12 m + f.  Every lane writes its 12
-// fields to its LDS slot, then lane ls stores the group's entries q gs + ls,
-// q < 12: consecutive lanes write consecutive 8-byte values.  Only indices in
-// [lo, hi) are written, and only by lanes with `active` set.  Called by every
-// lane of the wave (it synchronises the wave).
-template <bool F64, int LGS>
-__device__ __forceinline__ void stage_store(const uint32_t (&d)[NW], uint64_t* __restrict__ stage,
-                                            uint32_t tid_blk, uint32_t ls, int64_t jb, int64_t lo,
-                                            int64_t hi, bool active, uint64_t* __restrict__ out) {
+// consecutive blocks; lane ls holds the group's block ls and has written its
+// 12 fields to its LDS slot (convert_to_lds).  Field f of the group's block m
+// has output index jb + 12 m + f.  After a wave synchronisation lane ls
+// stores the group's entries q gs + ls, q < 12: consecutive lanes write
+// consecutive 8-byte values.  Only indices in [lo, hi) are written, and only
+// by lanes with `active` set.  Called by every lane of the wave.
+template <int LGS>
+__device__ __forceinline__ void group_store(const uint64_t* __restrict__ stage, uint32_t tid_blk, uint32_t ls,
+                                            int64_t jb, int64_t lo, int64_t hi, bool active,
+                                            uint64_t* __restrict__ out) {
   constexpr uint32_t gs = 1u << LGS;
-  uint64_t* mine = stage + (size_t)tid_blk * FIELDS;
-#pragma unroll
-  for (int f = 0; f < FIELDS; ++f) mine[f] = field_bits<F64>(d, f);
   wave_sync();
   const uint64_t* grp = stage + (size_t)(tid_blk - ls) * FIELDS + ls;
   if (active) {

@@ -1,0 +1,62 @@
+"""Serving loop: every request's values are the same alone and in the mix.
+
+The loop assigns each request the next window of its stream in arrival
+order; whatever batches, slots and overlaps the run produces, request k must
+hold exactly the values of that window (checked against a one-request plan
+run alone, and against the oracle on a sample).  Admission never lets the
+admitted outputs exceed the arena.
+"""
+import random
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2106_02504_amd as rlx
+from paper_2106_02504_amd.serve import Server
+
+pytestmark = pytest.mark.gpu
+
+
+def fifo_starts(stream_id, count, arrival):
+    order = np.argsort(arrival, kind="stable")
+    cur = {}
+    start = np.zeros(len(count), dtype=np.uint64)
+    for r in order:
+        s = int(stream_id[r])
+        start[r] = cur.get(s, 0)
+        cur[s] = cur.get(s, 0) + int(count[r])
+    return start
+
+
+@pytest.mark.parametrize("slots,arena", [(1, 1 << 18), (3, 1 << 16), (4, 1 << 22)])
+def test_serve_results_equal_alone(slots, arena):
+    rng = np.random.default_rng(slots)
+    n = 300
+    p = 218
+    pool = 64
+    arrival = np.cumsum(rng.exponential(1.0 / 20000.0, size=n))
+    stream_id = rng.integers(0, pool, size=n).astype(np.uint64)
+    count = np.floor(10.0 ** (1 + 3.5 * rng.random(n))).astype(np.uint64)
+    srv = Server(pool=pool, p=p, arena_values=arena, slots=slots, lanes=8, seg_blocks=64)
+    stats, outs = srv.run(arrival, stream_id, count, keep_outputs=True)
+    start = fifo_starts(stream_id, count, arrival)
+    assert np.array_equal(stats.extra["starts"], start)
+    assert stats.arena_peak_values <= arena
+    assert np.isfinite(stats.latencies_ms).all() and (stats.latencies_ms >= -1.0).all()
+    # alone: each request as a one-request plan over the same records
+    st = srv.states
+    for k in range(n):
+        req = rlx.requests_array([int(stream_id[k])], [int(start[k])], [int(count[k])], p)
+        out = torch.empty(int(count[k]), dtype=torch.float64, device=st.device)
+        plan = rlx.Plan(req, lanes=4, seg_blocks=16)
+        plan.generate_f64(st, out)
+        assert np.array_equal(outs[k], out.cpu().numpy()), k
+        plan.close()
+    # oracle on a sample
+    for k in random.Random(slots).sample(range(n), 12):
+        x0 = O.seed(int(stream_id[k]), p)
+        exp = O.window(x0, p, int(start[k]), int(count[k]))
+        assert (outs[k] * 2.0 ** 48).astype(np.int64).tolist() == exp
+    srv.close()
