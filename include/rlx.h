@@ -75,6 +75,7 @@ enum {
 #define RLX_ERR_BAD_P    0x1u   /* record's p differs from the call's p */
 #define RLX_ERR_BAD_POS  0x2u   /* record's pos > 11 */
 #define RLX_ERR_BAD_X    0x4u   /* record's X >= m */
+#define RLX_ERR_NOT_CANONICAL 0x8u  /* imported RANLUX state is not canonical */
 
 /* Message for an error code (static string). */
 const char *rlx_strerror(int code);
@@ -128,6 +129,35 @@ int rlx_generate_u64(rlx_state *states, uint64_t n, uint64_t count,
 int rlx_generate_f64_trace(rlx_state *states, uint64_t n, uint64_t count,
                            double *out, uint64_t *trace,
                            uint64_t steps_per_stream, uint32_t p, void *stream);
+
+/* Skip-ahead counted in values: advance every record (luxury level p) by
+ * v = values[i] (or values0 when values == NULL) draws, i.e. to position
+ * pos + v: x <- A_p^((pos + v) / 12) x, pos <- (pos + v) mod 12. */
+int rlx_skip_values(rlx_state *states, uint64_t n, const uint64_t *values,
+                    uint64_t values0, uint32_t p, void *stream);
+
+/* ---- RANLUX-form state (section 2: the final version stores the 24
+ * RANLUX numbers packed in 576 bits plus the carry bit) ------------------ */
+
+/* For every record: packed[9 i .. 9 i + 8] = D = floor(X 2^576 / m), the 24
+ * RANLUX numbers of the current step (oldest in the least significant 24
+ * bits), carry[i] = the RANLUX carry c = X - D + floor(D / 2^336) (0 or 1),
+ * pos[i] = the record's pos (may be NULL).  Records with X >= m are flagged
+ * RLX_ERR_BAD_X and their outputs left unwritten. */
+int rlx_export_ranlux(const rlx_state *states, uint64_t n, uint64_t *packed,
+                      uint32_t *carry, uint32_t *pos, void *stream);
+
+/* The inverse: states[i] <- X = D - floor(D / 2^336) + c with D =
+ * packed[9 i ..], c = carry[i], pos = pos[i] (or 0 when pos == NULL), p.
+ * A state is imported only if it is a RANLUX state of this generator in
+ * canonical form -- X < m (which excludes the degenerate state with every
+ * number 2^24 - 1 and carry 1, X = m) and exporting X gives back (D, c);
+ * otherwise the record is left unchanged and RLX_ERR_NOT_CANONICAL (or
+ * RLX_ERR_BAD_POS for pos > 11) is flagged.  Any SWB state becomes canonical
+ * after 24 steps of the subtract-with-borrow recurrence. */
+int rlx_import_ranlux(rlx_state *states, uint64_t n, const uint64_t *packed,
+                      const uint32_t *carry, const uint32_t *pos, uint32_t p,
+                      void *stream);
 
 /* Lanes per stream record used by the generate calls.  G lanes of one
  * record interleave its generator steps (lane l takes steps l, l + G, ...,

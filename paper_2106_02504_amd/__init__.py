@@ -25,7 +25,7 @@ import torch  # load torch's HIP runtime first: librlx.so binds to the same one
 __all__ = [
     "RlxError", "lib", "new_states", "prepare", "init_streams", "skip",
     "generate_f64", "generate_u64", "generate_f64_trace", "check_errors",
-    "set_lanes_per_stream", "lanes_per_stream", "REQUEST_DTYPE", "requests_array", "Plan", "plan_dry_run",
+    "set_lanes_per_stream", "lanes_per_stream", "skip_values", "export_ranlux", "import_ranlux", "REQUEST_DTYPE", "requests_array", "Plan", "plan_dry_run",
     "constants", "test_mulmod", "test_pow", "test_to_ranlux",
     "test_generate_u64_general", "STATE_WORDS",
 ]
@@ -45,6 +45,9 @@ _SIGS = {
     "rlx_prepare": (_int, [_u32, _vp]),
     "rlx_init_streams": (_int, [_vp, _u64, _vp, _u64, _u32, _vp]),
     "rlx_skip": (_int, [_vp, _u64, _vp, _u64, _u32, _vp]),
+    "rlx_skip_values": (_int, [_vp, _u64, _vp, _u64, _u32, _vp]),
+    "rlx_export_ranlux": (_int, [_vp, _u64, _vp, _vp, _vp, _vp]),
+    "rlx_import_ranlux": (_int, [_vp, _u64, _vp, _vp, _vp, _u32, _vp]),
     "rlx_generate_f64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_u64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_f64_trace": (_int, [_vp, _u64, _u64, _vp, _vp, _u64, _u32, _vp]),
@@ -156,6 +159,44 @@ def skip(states: torch.Tensor, steps, p: int) -> torch.Tensor:
         ptr, s0 = None, int(steps)
     with torch.cuda.device(states.device):
         _check(lib().rlx_skip(states.data_ptr(), n, ptr, s0, p, _stream()), "rlx_skip")
+    return states
+
+
+def skip_values(states: torch.Tensor, values, p: int) -> torch.Tensor:
+    """Advance every record by `values` draws (an int, or a device tensor of
+    n uint64/int64)."""
+    n = _need_states(states)
+    if isinstance(values, torch.Tensor):
+        _need_u64_vector(values, n, "values")
+        ptr, v0 = values.data_ptr(), 0
+    else:
+        ptr, v0 = None, int(values)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_skip_values(states.data_ptr(), n, ptr, v0, p, _stream()), "rlx_skip_values")
+    return states
+
+
+def export_ranlux(states: torch.Tensor):
+    """(packed [n, 9] int64 = the 24 RANLUX numbers of the current step,
+    carry [n] int32, pos [n] int32) of every record (section 2)."""
+    n = _need_states(states)
+    packed = torch.zeros((n, 9), dtype=torch.int64, device=states.device)
+    carry = torch.zeros((n,), dtype=torch.int32, device=states.device)
+    pos = torch.zeros((n,), dtype=torch.int32, device=states.device)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_export_ranlux(states.data_ptr(), n, packed.data_ptr(), carry.data_ptr(), pos.data_ptr(),
+                                       _stream()), "rlx_export_ranlux")
+    return packed, carry, pos
+
+
+def import_ranlux(states: torch.Tensor, packed: torch.Tensor, carry: torch.Tensor, p: int,
+                  pos: torch.Tensor | None = None) -> torch.Tensor:
+    """Records from RANLUX-form states (canonical ones only; others are
+    flagged in the error word and left unchanged)."""
+    n = _need_states(states)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_import_ranlux(states.data_ptr(), n, packed.data_ptr(), carry.data_ptr(), _ptr(pos), p,
+                                       _stream()), "rlx_import_ranlux")
     return states
 
 

@@ -110,10 +110,12 @@ __global__ __launch_bounds__(BLOCK) void k_init(rlx_state* __restrict__ st, uint
   store_record(st, i, x, 0u, p);
 }
 
+// by_values = 0: skip `steps` generator steps (pos unchanged); 1: skip that
+// many values (pos + v = 12 k + pos', k steps, new pos').
 __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint64_t n,
                                                 const uint64_t* __restrict__ steps, uint64_t steps0,
                                                 uint32_t p, const uint32_t* __restrict__ T,
-                                                uint32_t* __restrict__ err) {
+                                                uint32_t* __restrict__ err, int by_values) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t x[NW], pos, sp;
@@ -123,7 +125,13 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
     atomicOr(err, bad);
     return;
   }
-  const uint64_t k = steps ? steps[i] : steps0;
+  uint64_t k = steps ? steps[i] : steps0;
+  if (by_values) {
+    const uint64_t v = k;
+    const uint32_t r = pos + (uint32_t)(v % FIELDS);
+    k = v / FIELDS + r / FIELDS;
+    pos = r % FIELDS;
+  }
   for (int nib = 0; nib < 16 && (k >> (4 * nib)) != 0; ++nib) {
     const uint32_t v = (uint32_t)(k >> (4 * nib)) & 15u;
     if (v == 0) continue;
@@ -226,6 +234,82 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
     }
     if (__any(live && t + G <= nadv)) step(x, constant_table(ctab), force, SgprBarrier());
   }
+}
+
+// ---------------------------------------------------------------------------
+// RANLUX-form state: export and import (section 2)
+
+__device__ __forceinline__ void load9w(const uint64_t* __restrict__ src, uint32_t (&x)[NW]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const uint64_t v = src[k];
+    x[2 * k] = (uint32_t)v;
+    x[2 * k + 1] = (uint32_t)(v >> 32);
+  }
+}
+
+__device__ __forceinline__ void store9w(uint64_t* __restrict__ dst, const uint32_t (&x)[NW]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) dst[k] = ((uint64_t)x[2 * k + 1] << 32) | x[2 * k];
+}
+
+__global__ __launch_bounds__(BLOCK) void k_export(const rlx_state* __restrict__ st, uint64_t n,
+                                                  uint64_t* __restrict__ packed, uint32_t* __restrict__ carry,
+                                                  uint32_t* __restrict__ posout, uint32_t* __restrict__ err) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t x[NW], pos, sp, d[NW];
+  load_record(st, i, x, pos, sp);
+  if (geq_m(x)) {
+    atomicOr(err, RLX_ERR_BAD_X);
+    return;
+  }
+  to_ranlux(x, d, false);
+  store9w(packed + i * 9, d);
+  carry[i] = ranlux_carry(x, d);
+  if (posout) posout[i] = pos;
+}
+
+// X = D - floor(D / 2^336) + c, accepted when X < m and X exports to (D, c).
+__global__ __launch_bounds__(BLOCK) void k_import(rlx_state* __restrict__ st, uint64_t n,
+                                                  const uint64_t* __restrict__ packed,
+                                                  const uint32_t* __restrict__ carry,
+                                                  const uint32_t* __restrict__ posin, uint32_t p,
+                                                  uint32_t* __restrict__ err) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t d[NW], x[NW];
+  load9w(packed + i * 9, d);
+  const uint32_t c = carry[i];
+  const uint32_t pos = posin ? posin[i] : 0u;
+  if (pos > 11) {
+    atomicOr(err, RLX_ERR_BAD_POS);
+    return;
+  }
+  // X = D - (D >> 336) + c; D >> 336 = window of D from word 10, bit 16
+  uint32_t br = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) x[k] = subb(d[k], window32(d, 10 + k, 16), br);
+  uint32_t cy = c > 1u ? 2u : c;  // a carry other than 0/1 fails the round trip below
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint64_t v = (uint64_t)x[k] + cy;
+    x[k] = (uint32_t)v;
+    cy = (uint32_t)(v >> 32);
+  }
+  bool ok = (br == 0) && (cy == 0) && !geq_m(x);
+  if (ok) {
+    uint32_t d2[NW];
+    to_ranlux(x, d2, false);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) ok = ok && d2[k] == d[k];
+    ok = ok && ranlux_carry(x, d2) == c;
+  }
+  if (!ok) {
+    atomicOr(err, RLX_ERR_NOT_CANONICAL);
+    return;
+  }
+  store_record(st, i, x, pos, p);
 }
 
 // ---------------------------------------------------------------------------
@@ -497,7 +581,54 @@ int rlx_skip(rlx_state* states, uint64_t n, const uint64_t* steps, uint64_t step
   uint32_t* err;
   rc = error_word(s, &err);
   if (rc) return rc;
-  k_skip<<<grid, BLOCK, 0, s>>>(states, n, steps, steps0, p, t.T, err);
+  k_skip<<<grid, BLOCK, 0, s>>>(states, n, steps, steps0, p, t.T, err, 0);
+  return launch_status();
+}
+
+int rlx_skip_values(rlx_state* states, uint64_t n, const uint64_t* values, uint64_t values0, uint32_t p,
+                    void* stream) {
+  if (n == 0) return RLX_OK;
+  if (!states || !valid_p(p) || !aligned(states, 16)) return RLX_EINVAL;
+  if (values && !aligned(values, 8)) return RLX_EINVAL;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  hipStream_t s = as_stream(stream);
+  Tables t;
+  int rc = tables(p, s, &t);
+  if (rc) return rc;
+  uint32_t* err;
+  rc = error_word(s, &err);
+  if (rc) return rc;
+  k_skip<<<grid, BLOCK, 0, s>>>(states, n, values, values0, p, t.T, err, 1);
+  return launch_status();
+}
+
+int rlx_export_ranlux(const rlx_state* states, uint64_t n, uint64_t* packed, uint32_t* carry, uint32_t* pos,
+                      void* stream) {
+  if (n == 0) return RLX_OK;
+  if (!states || !packed || !carry || !aligned(states, 16) || !aligned(packed, 8)) return RLX_EINVAL;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  hipStream_t s = as_stream(stream);
+  uint32_t* err;
+  int rc = error_word(s, &err);
+  if (rc) return rc;
+  k_export<<<grid, BLOCK, 0, s>>>(states, n, packed, carry, pos, err);
+  return launch_status();
+}
+
+int rlx_import_ranlux(rlx_state* states, uint64_t n, const uint64_t* packed, const uint32_t* carry,
+                      const uint32_t* pos, uint32_t p, void* stream) {
+  if (n == 0) return RLX_OK;
+  if (!states || !packed || !carry || !valid_p(p) || !aligned(states, 16) || !aligned(packed, 8))
+    return RLX_EINVAL;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  hipStream_t s = as_stream(stream);
+  uint32_t* err;
+  int rc = error_word(s, &err);
+  if (rc) return rc;
+  k_import<<<grid, BLOCK, 0, s>>>(states, n, packed, carry, pos, p, err);
   return launch_status();
 }
 
