@@ -66,7 +66,7 @@ __global__ __launch_bounds__(64) void k_tab_fill(uint32_t* __restrict__ T) {
   store_words(T + ((size_t)i * TAB_COLS + j) * NW, r);
 }
 
-// C_g[j] = A_p^(2^g) 2^(27 j) mod m: block g (g < 64) builds the folded
+// C_g[j] = A_p^(2^g) 2^(o_j) mod m: block g (g < 64) builds the folded
 // multiplier of a step by 2^g generator steps, one lane per row j.  A_p^(2^g)
 // is a single entry of T: 2^g = v 16^i with v in {1, 2, 4, 8}.
 __global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T, uint32_t* __restrict__ C) {
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T,
   if (j >= NL) return;
   uint32_t a[NW], pw[NW], r[NW];
   load_words(T + ((size_t)(g >> 2) * TAB_COLS + (1u << (g & 3))) * NW, a);
-  const int bit = LB * j;
+  const int bit = limb_offset(j);
 #pragma unroll
   for (int k = 0; k < NW; ++k) pw[k] = (k == (bit >> 5)) ? (1u << (bit & 31)) : 0u;
   mulmod_generic(a, pw, r);

@@ -12,12 +12,13 @@
 //
 //  * step(): the generator step X <- A X mod m for a multiplier A that is the
 //    same for the whole launch.  The reduction is folded into a constant
-//    table: C_j = A 2^(27 j) mod m (j < 22), so that with X split into 22
-//    limbs l_j of 27 bits, A X = sum_j l_j C_j (mod m).  Each product
-//    l_j * C_j[k] is below 2^59 and every column sum of 22 of them is below
-//    2^64, so the product runs on v_mad_u64_u32 with no carry handling; one
-//    32-bit word remains above 2^576 and is folded with 2^576 = 2^240 - 1
-//    (mod m).
+//    table: C_j = A 2^(o_j) mod m (j < 21), so that with X split into 21
+//    limbs l_j of w_j bits at bit offsets o_j, A X = sum_j l_j C_j (mod m).
+//    The widths are ten of 28 bits, ten of 27 and one of 26 (576 in all);
+//    since sum_j 2^(w_j) <= 2^32, every column sum of products
+//    l_j * C_j[k] (32-bit words C_j[k]) stays below 2^64, so the product is
+//    378 v_mad_u64_u32 with no carry handling.  One 32-bit word remains
+//    above 2^576 and is folded with 2^576 = 2^240 - 1 (mod m).
 //
 // Both end in the canonical residue.  Rare carries, borrows and the final
 // comparison with m take a general branch that is exact for every input; the
@@ -40,9 +41,12 @@
 namespace rlx {
 
 constexpr int NW = 18;        // 32-bit words of a 576-bit number
-constexpr int NL = 22;        // 27-bit limbs of X in the constant-multiplier step
-constexpr int LB = 27;        // limb bits
-constexpr uint32_t LMASK = (1u << LB) - 1u;
+constexpr int NL = 21;        // limbs of X in the constant-multiplier step
+
+// width and bit offset of limb j: ten 28-bit, ten 27-bit, one 26-bit limb
+RLX_HD constexpr int limb_bits(int j) { return j < 10 ? 28 : (j < 20 ? 27 : 26); }
+RLX_HD constexpr int limb_offset(int j) { return j <= 10 ? 28 * j : 280 + 27 * (j - 10); }
+static_assert(limb_offset(NL - 1) + limb_bits(NL - 1) == 576, "limbs cover 576 bits");
 
 // m = 2^576 - 2^240 + 1
 RLX_HD uint32_t m_word(int k) {
@@ -217,12 +221,12 @@ RLX_HD void mulmod_generic(const uint32_t (&x)[NW], const uint32_t (&y)[NW], uin
 // ---------------------------------------------------------------------------
 // the generator step with a launch-uniform multiplier
 
-// 22 limbs of 27 bits of X (< 2^576: the top limb has 9 bits).
-RLX_HD void unpack27(const uint32_t (&w)[NW], uint32_t (&l)[NL]) {
+// The 21 limbs of X (widths limb_bits, offsets limb_offset).
+RLX_HD void unpack_limbs(const uint32_t (&w)[NW], uint32_t (&l)[NL]) {
 #pragma unroll
   for (int j = 0; j < NL; ++j) {
-    const int bit = LB * j;
-    l[j] = window32(w, bit >> 5, bit & 31) & LMASK;
+    const int bit = limb_offset(j);
+    l[j] = window32(w, bit >> 5, bit & 31) & ((1u << limb_bits(j)) - 1u);
   }
 }
 
@@ -232,14 +236,14 @@ struct Plain {
   RLX_HD uint32_t operator()(uint32_t v, uint32_t) const { return v; }
 };
 
-// X <- A X mod m.  `tab` holds C_j = A 2^(27 j) mod m, row j = 18 words
+// X <- A X mod m.  `tab` holds C_j = A 2^(o_j) mod m, row j = 18 words
 // (kernels pass a pointer into the read-only constant address space, so the
 // rows are fetched with scalar loads).  Returns through `x` the canonical
 // residue.
 template <class Launder = Plain, class TabPtr = const uint32_t*>
 RLX_HD void step(uint32_t (&x)[NW], TabPtr tab, bool force_general, Launder launder = Launder()) {
   uint32_t l[NL];
-  unpack27(x, l);
+  unpack_limbs(x, l);
   uint64_t s[NW];
   // Rows of the table are read with scalar loads one row ahead of the
   // multiply-adds that use them.  Scalar loads complete out of order, so a

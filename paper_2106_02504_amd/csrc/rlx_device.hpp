@@ -13,7 +13,7 @@ namespace rlx {
 //   T[i][j] = A_p^(j 16^i) mod m, i < 40, j < 16 (18 words each): 4-bit
 //             windows of a 160-bit exponent; rows 0..15 serve skips of
 //             k < 2^64 steps, rows 24..39 serve seeds (exponent 2^96 id).
-//   C[g][j] = A_p^(2^g) 2^(27 j) mod m, g < 64, j < 22: the folded
+//   C[g][j] = A_p^(2^g) 2^(o_j) mod m, g < 64, j < 21 (o_j = limb_offset(j)): the folded
 //             multiplier of a step by 2^g generator steps (see step()).
 constexpr int TAB_ROWS = 40;
 constexpr int TAB_COLS = 16;

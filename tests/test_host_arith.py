@@ -24,6 +24,15 @@ def from_words(ws):
     return sum(int(w, 16) << (32 * k) for k, w in enumerate(ws))
 
 
+def limb_offsets():
+    """Bit offsets of the 21 limbs of the library's constant-multiplier step
+    (ten 28-bit, ten 27-bit, one 26-bit limb): its table rows are
+    A 2^offset mod m."""
+    widths = [28] * 10 + [27] * 10 + [26]
+    assert sum(widths) == 576 and sum(1 << w for w in widths) <= 1 << 32
+    return [sum(widths[:j]) for j in range(21)]
+
+
 def setw(x, k, v):
     return (x & ~(0xFFFFFFFF << (32 * k))) | (v << (32 * k))
 
@@ -60,8 +69,8 @@ def test_host_build_matches_oracle(harness, tmp_path, p):
     rng = random.Random(p)
     a_p = O.multiplier(p)
     tab = []
-    for j in range(22):
-        tab += words(a_p * (1 << (27 * j)) % O.M)
+    for off in limb_offsets():
+        tab += words(a_p * (1 << off) % O.M)
     xs = cases(rng)
     # step results that land on chosen values (top word all ones, m - 1, ...)
     inv = pow(a_p, -1, O.M)
