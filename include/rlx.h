@@ -36,7 +36,9 @@
  *              pos > 11, or a luxury level different from `p`) are skipped --
  *              their outputs are left unwritten -- and flagged in the device
  *              error word, which rlx_check_errors() reads and clears.
- *   Sizes      n = 0 or count = 0 is a no-op returning RLX_OK.
+ *   Sizes      n = 0 or count = 0 is a no-op returning RLX_OK.  One call of
+ *              a generate entry point takes at most RLX_MAX_STREAMS records
+ *              and RLX_MAX_COUNT values per record (RLX_EINVAL beyond).
  *   Threads    Entry points may be called from several host threads.
  *   Overlap    Output arrays must not overlap the state array or each other.
  */
@@ -70,6 +72,13 @@ enum {
     RLX_ENOMEM = 3,   /* table allocation failed */
     RLX_ESTATE = 4    /* a kernel found an invalid stream record */
 };
+
+/* Size limits of one generate call (2^35 doubles are 256 GiB, more than
+ * one device holds for a single record). */
+#define RLX_MAX_STREAMS 0xFFFFFFFFull
+#define RLX_MAX_COUNT   (1ull << 35)
+/* Largest segment length of a batch plan, in generator steps. */
+#define RLX_MAX_SEG_BLOCKS (1ull << 26)
 
 /* Error-word bits reported by rlx_check_errors(). */
 #define RLX_ERR_BAD_P    0x1u   /* record's p differs from the call's p */
@@ -119,6 +128,17 @@ int rlx_generate_f64(rlx_state *states, uint64_t n, uint64_t count,
  * zero-extended to 64 bits (section 2.4's integer draw). */
 int rlx_generate_u64(rlx_state *states, uint64_t n, uint64_t count,
                      uint64_t *out, uint32_t p, void *stream);
+
+/* Standard normal doubles: the value at stream position s is the
+ * Box-Muller transform of the field pair of its step, positions s & ~1 and
+ * s | 1 (u1, u2 their doubles): r cos(2 pi u2) for even s and r sin(2 pi u2)
+ * for odd s, r = sqrt(-2 ln(1 - u1)).  So each value depends on its position
+ * only, and count normals advance the record by count positions, as count
+ * uniforms do.  The transcendental functions are the device's (a few ulp),
+ * so results are not bit-identical to a CPU evaluation.  The paper leaves
+ * distributions to the framework around the engine (section 2.4). */
+int rlx_generate_normal_f64(rlx_state *states, uint64_t n, uint64_t count,
+                            double *out, uint32_t p, void *stream);
 
 /* rlx_generate_f64 that also writes the LCG state of every step it visits:
  * trace[(i * steps_per_stream + t) * 9 + w], t = 0 is the state on entry and
@@ -192,7 +212,7 @@ typedef struct rlx_request {
 
 /* A plan holds the device descriptors of a batch (library-owned device
  * memory).  The planner splits every request into segments of at most
- * `seg_blocks` generator steps, gives each segment `lanes` (a power of two <=
+ * `seg_blocks` (1 .. RLX_MAX_SEG_BLOCKS) generator steps, gives each segment `lanes` (a power of two <=
  * 64) lanes that interleave its steps, and groups segments of one luxury
  * level into work items of 64 lanes.  At most 16 distinct luxury levels per
  * plan. */

@@ -24,7 +24,7 @@ import torch  # load torch's HIP runtime first: librlx.so binds to the same one
 
 __all__ = [
     "RlxError", "lib", "new_states", "prepare", "init_streams", "skip",
-    "generate_f64", "generate_u64", "generate_f64_trace", "check_errors",
+    "generate_f64", "generate_u64", "generate_normal_f64", "generate_f64_trace", "check_errors",
     "set_lanes_per_stream", "lanes_per_stream", "skip_values", "export_ranlux", "import_ranlux", "REQUEST_DTYPE", "requests_array", "Plan", "plan_dry_run",
     "constants", "test_mulmod", "test_pow", "test_to_ranlux",
     "test_generate_u64_general", "STATE_WORDS",
@@ -50,6 +50,7 @@ _SIGS = {
     "rlx_import_ranlux": (_int, [_vp, _u64, _vp, _vp, _vp, _u32, _vp]),
     "rlx_generate_f64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_u64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
+    "rlx_generate_normal_f64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_f64_trace": (_int, [_vp, _u64, _u64, _vp, _vp, _u64, _u32, _vp]),
     "rlx_check_errors": (_int, [_vp, ctypes.POINTER(_u32)]),
     "rlx_set_lanes_per_stream": (_int, [_u32]),
@@ -224,6 +225,17 @@ def generate_u64(states: torch.Tensor, count: int, p: int, out: torch.Tensor | N
     out = _out(states, count, torch.int64, out)
     with torch.cuda.device(states.device):
         _check(lib().rlx_generate_u64(states.data_ptr(), n, count, out.data_ptr(), p, _stream()), "rlx_generate_u64")
+    return out
+
+
+def generate_normal_f64(states: torch.Tensor, count: int, p: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """`count` standard normal doubles per record, shape [n, count]: Box-Muller
+    on the field pair of each position's step (device transcendentals)."""
+    n = _need_states(states)
+    out = _out(states, count, torch.float64, out)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_generate_normal_f64(states.data_ptr(), n, count, out.data_ptr(), p, _stream()),
+               "rlx_generate_normal_f64")
     return out
 
 

@@ -4,7 +4,7 @@
 //   k_tab_base / k_tab_fill / k_tab_fold   per-luxury-level constant tables
 //   k_init                                 seeding        (section 2.4)
 //   k_skip                                 skip-ahead     (section 2.4)
-//   k_generate<F64|U64, trace, LGS>        draw values    (sections 2.1-2.3)
+//   k_generate<U64|F64|NORMAL, trace, LGS> draw values (sections 2.1-2.3)
 //   k_test_*                               generic arithmetic for tests
 // The batched persistent kernel and its planner are in rlx_batch.hip.
 #include <hip/hip_runtime.h>
@@ -161,26 +161,29 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
 //
 // The record is advanced eagerly: the lane holding block nadv writes it back
 // with pos = (pos + count) mod 12.
-template <bool F64, bool TRACE, int LGS>
-__global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, uint64_t n,
+template <Out K, bool TRACE, int LGS>
+__global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, uint32_t n,
                                                     uint64_t count, uint64_t* __restrict__ out,
                                                     uint64_t* __restrict__ trace, uint64_t trace_steps,
                                                     const uint32_t* __restrict__ ctabs, uint32_t lg,
                                                     uint32_t p, uint32_t* __restrict__ err,
                                                     int force_general) {
+  // Per-lane state kept across the loop is x plus four 32-bit words (record
+  // index, lane, pos, last block): the host limits n < 2^32 and
+  // count <= RLX_MAX_COUNT, so record and block indices fit in 32 bits.
+  // Everything else is recomputed per iteration, which keeps the kernel at
+  // eight waves per SIMD.
   constexpr bool STAGED = LGS > 0;
   constexpr uint32_t gs = 1u << LGS;  // lanes of a record inside one wave
-  __shared__ uint64_t stage[STAGED ? BLOCK * FIELDS : 1];
-  const uint32_t tid_blk = threadIdx.x;
-  const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + tid_blk;
-  const uint64_t G = 1ull << lg;
-  const uint64_t i = tid >> lg;
-  const uint32_t l = (uint32_t)(tid & (G - 1));
+  __shared__ __align__(16) uint64_t stage[STAGED ? BLOCK * SLOT_VALUES : 2];
+  const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t i = (uint32_t)(tid >> lg);
+  const uint32_t l = (uint32_t)tid & ((1u << lg) - 1u);
   const bool force = force_general != 0;
 
   uint32_t x[NW];
   uint32_t pos = 0, sp = 0;
-  bool active = i < n;
+  bool active = (tid >> lg) < n;
   if (active) {
     load_record(st, i, x, pos, sp);
     const uint32_t bad = check_record(x, pos, sp, p);
@@ -193,46 +196,43 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
     set_one(x);
     pos = 0;
   }
-  const uint64_t total = pos + count;
-  const uint64_t nadv = total / FIELDS;
-  const uint32_t rem = (uint32_t)(total % FIELDS);
+  const uint32_t nadv = (uint32_t)((pos + count) / FIELDS);
 
   // lane l starts at block l: X_l = A^l X_0 (bits 6 and up of l are the
   // same for the whole wave)
   if (STAGED) advance(x, l, ctabs, force);
   const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * FOLD_ROW_WORDS;
 
-  uint64_t* row = out + i * count;
-  uint64_t* tr = TRACE ? trace + i * trace_steps * 9 : nullptr;
-  const uint32_t ls = l & (gs - 1);
-
-  for (uint64_t k = 0;; ++k) {
-    const uint64_t t = l + (k << lg);
+  for (uint32_t k = 0;; ++k) {
+    const uint32_t t = l + (k << lg);
     const bool live = active && t <= nadv;
     if (!__any(live)) break;
     if (live) {
-      if (TRACE) put_trace(tr + t * 9, x);
-      if (t == nadv) store_record(st, i, x, rem, sp);
+      if (TRACE) put_trace(trace + ((uint64_t)i * trace_steps + t) * 9, x);
+      if (t == nadv) store_record(st, i, x, (uint32_t)((pos + count) % FIELDS), p);
     }
+    uint64_t* const row = out + (uint64_t)i * count;
     if (!STAGED) {
       uint32_t d[NW];
       to_ranlux(x, d, force);
       if (live) {
-        const int64_t jb = (int64_t)(t * FIELDS) - (int64_t)pos;
+        const int64_t jb = (int64_t)((uint64_t)t * FIELDS) - (int64_t)pos;
 #pragma unroll
         for (int f = 0; f < FIELDS; ++f) {
           const int64_t j = jb + f;
-          if (j >= 0 && (uint64_t)j < count) row[j] = field_bits<F64>(d, f);
+          if (j >= 0 && (uint64_t)j < count) row[j] = field_bits<K>(d, f);
         }
       }
     } else {
-      convert_to_lds<F64>(x, stage + (size_t)tid_blk * FIELDS, force);
+      const uint32_t tid_blk = threadIdx.x;
+      const uint32_t ls = l & (gs - 1);
+      convert_to_lds<K>(x, stage + (size_t)tid_blk * SLOT_VALUES, force);
       // the group's blocks t - ls .. t - ls + gs - 1 hold output indices
       // from jb on
-      const int64_t jb = (int64_t)((t - ls) * FIELDS) - (int64_t)pos;
-      group_store<LGS>(stage, tid_blk, ls, jb, 0, (int64_t)count, active, row);
+      const int64_t jb = (int64_t)((uint64_t)(t - ls) * FIELDS) - (int64_t)pos;
+      group_store<LGS>(stage, tid_blk, ls, jb, count, active, row);
     }
-    if (__any(live && t + G <= nadv)) step(x, constant_table(ctab), force, SgprBarrier());
+    if (__any(live && t + (1u << lg) <= nadv)) step(x, constant_table(ctab), force, SgprBarrier());
   }
 }
 
@@ -460,14 +460,16 @@ namespace {
 std::atomic<uint32_t> g_lanes_override{0};
 
 // Lanes per record: the largest power of two G <= 4096 such that the launch
-// stays within about eight waves per SIMD (2^19 lanes on 256 CUs) and every
-// lane still takes at least 24 generator steps, which keeps the per-lane
-// start-up (one folded step per set bit of the lane index) small.
+// stays within sixteen waves per SIMD (2^20 lanes on 256 CUs) and every lane
+// still takes at least 16 generator steps.  A wave pays one folded step per
+// bit of G at start-up, so G trades start-up work against the length of the
+// contiguous runs each store instruction writes (16 G bytes per record);
+// on the many-streams shape G = 16 measured fastest.
 uint32_t auto_lanes(uint64_t n, uint64_t count) {
   const uint64_t steps = count / FIELDS + 1;
-  const uint64_t target = 1ull << 19;
+  const uint64_t target = 1ull << 20;
   uint64_t g = 1;
-  while (g < 4096 && n <= target / (g * 2) && steps / (g * 2) >= 24) g *= 2;
+  while (g < 4096 && n <= target / (g * 2) && steps / (g * 2) >= 16) g *= 2;
   return (uint32_t)g;
 }
 
@@ -476,12 +478,13 @@ uint32_t lanes_for(uint64_t n, uint64_t count) {
   return o ? o : auto_lanes(n, count);
 }
 
-template <bool F64, bool TRACE>
+template <Out K, bool TRACE>
 int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint64_t* trace,
                   uint64_t trace_steps, uint32_t p, void* stream, int force_general) {
   if (n == 0 || count == 0) return RLX_OK;
   if (!states || !out || !valid_p(p)) return RLX_EINVAL;
   if (!aligned(states, 16) || !aligned(out, 8)) return RLX_EINVAL;
+  if (n > RLX_MAX_STREAMS || count > RLX_MAX_COUNT) return RLX_EINVAL;
   if (count > UINT64_MAX / 8 / n) return RLX_EINVAL;
   if (TRACE) {
     if (!trace || !aligned(trace, 8)) return RLX_EINVAL;
@@ -505,7 +508,7 @@ int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint
   const uint32_t lgs = lg < 6 ? lg : 6;
 #define RLX_GEN(L)                                                                                    \
   case L:                                                                                             \
-    k_generate<F64, TRACE, L><<<grid, BLOCK, 0, s>>>(states, n, count, o, trace, trace_steps, t.C, lg, p, \
+    k_generate<K, TRACE, L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, trace, trace_steps, t.C, lg, p, \
                                                      err, force_general);                             \
     break;
   switch (lgs) {
@@ -634,23 +637,28 @@ int rlx_import_ranlux(rlx_state* states, uint64_t n, const uint64_t* packed, con
 
 int rlx_generate_f64(rlx_state* states, uint64_t n, uint64_t count, double* out, uint32_t p,
                      void* stream) {
-  return generate_impl<true, false>(states, n, count, out, nullptr, 0, p, stream, 0);
+  return generate_impl<Out::F64, false>(states, n, count, out, nullptr, 0, p, stream, 0);
 }
 
 int rlx_generate_u64(rlx_state* states, uint64_t n, uint64_t count, uint64_t* out, uint32_t p,
                      void* stream) {
-  return generate_impl<false, false>(states, n, count, out, nullptr, 0, p, stream, 0);
+  return generate_impl<Out::U64, false>(states, n, count, out, nullptr, 0, p, stream, 0);
+}
+
+int rlx_generate_normal_f64(rlx_state* states, uint64_t n, uint64_t count, double* out, uint32_t p,
+                            void* stream) {
+  return generate_impl<Out::NORMAL, false>(states, n, count, out, nullptr, 0, p, stream, 0);
 }
 
 int rlx_generate_f64_trace(rlx_state* states, uint64_t n, uint64_t count, double* out, uint64_t* trace,
                            uint64_t steps_per_stream, uint32_t p, void* stream) {
   if (n != 0 && count != 0 && !trace) return RLX_EINVAL;
-  return generate_impl<true, true>(states, n, count, out, trace, steps_per_stream, p, stream, 0);
+  return generate_impl<Out::F64, true>(states, n, count, out, trace, steps_per_stream, p, stream, 0);
 }
 
 int rlx_test_generate_u64_general(rlx_state* states, uint64_t n, uint64_t count, uint64_t* out,
                                   uint32_t p, void* stream) {
-  return generate_impl<false, false>(states, n, count, out, nullptr, 0, p, stream, 1);
+  return generate_impl<Out::U64, false>(states, n, count, out, nullptr, 0, p, stream, 1);
 }
 
 int rlx_set_lanes_per_stream(uint32_t lanes) {

@@ -71,13 +71,13 @@ __global__ void k_reset(Header* __restrict__ hdr) {
   if (threadIdx.x == 0 && blockIdx.x == 0) hdr->counter = 0;
 }
 
-template <bool F64, int LGS>
+template <Out K, int LGS>
 __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ st,
                                                  const Segment* __restrict__ segs,
                                                  const Item* __restrict__ items, Header* __restrict__ hdr,
                                                  uint64_t* __restrict__ out, uint32_t* __restrict__ err) {
   constexpr uint32_t G = 1u << LGS;
-  __shared__ uint64_t stage[BLOCK * FIELDS];
+  __shared__ __align__(16) uint64_t stage[BLOCK * SLOT_VALUES];
   const uint32_t tid_blk = threadIdx.x;
   const uint32_t lane = tid_blk & (WAVE - 1);
   const uint32_t team = lane >> LGS;
@@ -93,10 +93,12 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ s
     const uint32_t* __restrict__ ctabs = hdr->C[slot];
     const uint32_t p = __builtin_amdgcn_readfirstlane(hdr->p[slot]);
     bool active = team < item.nseg;
-    Segment sg{};
+    uint32_t si = item.seg0 + team;
+    uint32_t nblocks = 0;
     uint32_t x[NW];
+    uint64_t first = 0;  // this lane's first block: the segment's first + l
     if (active) {
-      sg = segs[item.seg0 + team];
+      const Segment& sg = segs[si];
       uint32_t pos, sp;
       load_record(st, sg.state, x, pos, sp);
       uint32_t bad = 0;
@@ -105,26 +107,40 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ s
       if (bad) {
         if (l == 0) atomicOr(err, bad);
         active = false;
+      } else {
+        nblocks = sg.nblocks;
+        first = sg.block + l;
       }
     }
-    if (!active) {
-      set_one(x);
-      sg.nblocks = 0;
-    }
-    // this lane's first block: sg.block + l
-    advance(x, active ? sg.block + l : 0, ctabs, false);
+    if (!active) set_one(x);
+    advance(x, first, ctabs, false);
     const uint32_t* __restrict__ ctab = ctabs + (size_t)LGS * FOLD_ROW_WORDS;
-    const int64_t lo = sg.lo > sg.jbase ? sg.lo : sg.jbase;
-    const int64_t end = sg.jbase + (int64_t)FIELDS * sg.nblocks;
-    const int64_t hi = sg.hi < end ? sg.hi : end;
+    // Output window of the segment: base[u] for u < span, with the
+    // segment's first field at u = rel (rel >= -11; span < 2^30 because
+    // segments hold at most 2^26 blocks).  Read after the lane set-up (the
+    // index is made opaque so the load is not merged with the one above),
+    // which keeps the window out of registers during it.
+    asm volatile("" : "+v"(si));
+    uint64_t* base = out;
+    uint32_t span = 0;
+    int32_t rel = 0;
+    if (active) {
+      const Segment& sg = segs[si];
+      const int64_t lo = sg.lo > sg.jbase ? sg.lo : sg.jbase;
+      const int64_t end = sg.jbase + (int64_t)FIELDS * nblocks;
+      const int64_t hi = sg.hi < end ? sg.hi : end;
+      base = out + lo;
+      span = hi > lo ? (uint32_t)(hi - lo) : 0u;
+      rel = (int32_t)(sg.jbase - lo);
+    }
     for (uint32_t k = 0;; ++k) {
       const uint32_t t = l + (k << LGS);
-      const bool live = active && t < sg.nblocks;
+      const bool live = active && t < nblocks;
       if (!__any(live)) break;
-      convert_to_lds<F64>(x, stage + (size_t)tid_blk * FIELDS, false);
-      const int64_t jb = sg.jbase + (int64_t)FIELDS * (t - l);
-      group_store<LGS>(stage, tid_blk, l, jb, lo, hi, active, out);
-      if (__any(live && t + G < sg.nblocks)) step(x, constant_table(ctab), false, SgprBarrier());
+      convert_to_lds<K>(x, stage + (size_t)tid_blk * SLOT_VALUES, false);
+      const int32_t u0 = rel + (int32_t)(FIELDS * (t - l));
+      group_store<LGS>(stage, tid_blk, l, u0, span, active, base);
+      if (__any(live && t + G < nblocks)) step(x, constant_table(ctab), false, SgprBarrier());
     }
   }
 }
@@ -257,7 +273,7 @@ void free_plan(rlx_plan* p) {
   delete p;
 }
 
-template <bool F64>
+template <Out K>
 int plan_launch(rlx_plan* plan, const rlx_state* states, void* out, void* stream) {
   if (!plan) return RLX_EINVAL;
   if (!states || !out || !aligned(states, 16) || !aligned(out, 8)) return RLX_EINVAL;
@@ -273,7 +289,7 @@ int plan_launch(rlx_plan* plan, const rlx_state* states, void* out, void* stream
   uint64_t* o = reinterpret_cast<uint64_t*>(out);
 #define RLX_BATCH(L)                                                                                      \
   case L:                                                                                                 \
-    k_batch<F64, L><<<(unsigned)blocks, BLOCK, 0, s>>>(states, plan->d_segs, plan->d_items, plan->d_hdr, o, \
+    k_batch<K, L><<<(unsigned)blocks, BLOCK, 0, s>>>(states, plan->d_segs, plan->d_items, plan->d_hdr, o, \
                                                        err);                                              \
     break;
   switch (plan->lg) {
@@ -294,7 +310,7 @@ int rlx_plan_create(rlx_plan** plan, const rlx_request* reqs, uint64_t n, uint32
   *plan = nullptr;
   if (n > 0 && !reqs) return RLX_EINVAL;
   if (lanes == 0 || lanes > (uint32_t)WAVE || (lanes & (lanes - 1)) != 0) return RLX_EINVAL;
-  if (seg_blocks == 0 || seg_blocks > 0x7FFFFFFFull) return RLX_EINVAL;
+  if (seg_blocks == 0 || seg_blocks > RLX_MAX_SEG_BLOCKS) return RLX_EINVAL;
   const uint32_t lg = (uint32_t)__builtin_ctz(lanes);
   Planned pl;
   int rc = plan_requests(reqs, n, lg, seg_blocks, &pl);
@@ -348,11 +364,11 @@ int rlx_plan_info(const rlx_plan* plan, uint64_t* segments, uint64_t* items, uin
 }
 
 int rlx_plan_generate_f64(rlx_plan* plan, const rlx_state* states, double* out, void* stream) {
-  return plan_launch<true>(plan, states, out, stream);
+  return plan_launch<Out::F64>(plan, states, out, stream);
 }
 
 int rlx_plan_generate_u64(rlx_plan* plan, const rlx_state* states, uint64_t* out, void* stream) {
-  return plan_launch<false>(plan, states, out, stream);
+  return plan_launch<Out::U64>(plan, states, out, stream);
 }
 
 int rlx_plan_dry_run(const rlx_request* reqs, uint64_t n, uint32_t lanes, uint64_t seg_blocks,
@@ -360,7 +376,7 @@ int rlx_plan_dry_run(const rlx_request* reqs, uint64_t n, uint32_t lanes, uint64
                      uint64_t max_segments) {
   if (n > 0 && !reqs) return RLX_EINVAL;
   if (lanes == 0 || lanes > (uint32_t)WAVE || (lanes & (lanes - 1)) != 0) return RLX_EINVAL;
-  if (seg_blocks == 0 || seg_blocks > 0x7FFFFFFFull) return RLX_EINVAL;
+  if (seg_blocks == 0 || seg_blocks > RLX_MAX_SEG_BLOCKS) return RLX_EINVAL;
   Planned pl;
   const int rc = plan_requests(reqs, n, (uint32_t)__builtin_ctz(lanes), seg_blocks, &pl);
   if (rc) return rc;

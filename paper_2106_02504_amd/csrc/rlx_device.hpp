@@ -128,53 +128,87 @@ __device__ __forceinline__ void advance(uint32_t (&x)[NW], uint64_t e, const uin
   }
 }
 
-template <bool F64>
-__device__ __forceinline__ uint64_t field_bits_w(uint32_t w0, uint32_t w1, uint32_t w2, int k) {
-  if (F64) {
-    const double v = field_f64_w(w0, w1, w2, k);
-    uint64_t b;
-    __builtin_memcpy(&b, &v, 8);
-    return b;
-  }
-  return field_u64_w(w0, w1, w2, k);
+// What a generate kernel writes for each position: the 48-bit integer, the
+// double v 2^-48, or a standard normal from the position's field pair.
+enum class Out { U64, F64, NORMAL };
+
+__device__ __forceinline__ double bits_to_f64(uint32_t lo, uint32_t hi) {
+  const uint64_t b = ((uint64_t)hi << 32) | lo;
+  double v;
+  __builtin_memcpy(&v, &b, 8);
+  return v;
 }
 
-// Write the 12 fields of one step to this lane's LDS slot.  D's words 0..8
-// are lo[0..8] and words 9..17 are hi[9..17] (after the fast conversion hi is
-// X itself; after the general one both are D).  Per lane, no synchronisation:
-// may run under divergent control flow.
-template <bool F64, int NLO>
-__device__ __forceinline__ void lds_fields(const uint32_t (&lo)[NLO], const uint32_t (&hi)[NW],
-                                           uint64_t* __restrict__ slot) {
-#pragma unroll
-  for (int f = 0; f < FIELDS; f += 2) {
-    const int i = f >> 1;
-    const uint32_t w0 = 3 * i < 9 ? lo[(3 * i) % NLO] : hi[3 * i];
-    const uint32_t w1 = 3 * i + 1 < 9 ? lo[(3 * i + 1) % NLO] : hi[3 * i + 1];
-    const uint32_t w2 = 3 * i + 2 < 9 ? lo[(3 * i + 2) % NLO] : hi[3 * i + 2];
-    slot[f] = field_bits_w<F64>(w0, w1, w2, f);
-    slot[f + 1] = field_bits_w<F64>(w0, w1, w2, f + 1);
-  }
+__device__ __forceinline__ uint64_t f64_bits(double v) {
+  uint64_t b;
+  __builtin_memcpy(&b, &v, 8);
+  return b;
 }
 
-// Convert X (section 2.3) and write its 12 fields to this lane's LDS slot.
-template <bool F64>
-__device__ __forceinline__ void convert_to_lds(const uint32_t (&x)[NW], uint64_t* __restrict__ slot,
-                                               bool force) {
-  uint32_t dlo[9];
-  if (!to_ranlux_fast(x, dlo, force)) {
-    lds_fields<F64>(dlo, x, slot);
+// The doubles of the field pair held in words (w0, w1, w2) (fields 2i and
+// 2i + 1 of a step: bits 0..47 and 48..95 of the three words), each v 2^-48
+// formed exactly as the bits of 1 + v 2^-48 minus 1.0.  The mantissa bits
+// are v << 4; for the odd field that is (w2:w1) >> 12 with the low four bits
+// cleared, and its exponent word is (0x3FF:w2) >> 12.
+__device__ __forceinline__ void pair_f64(uint32_t w0, uint32_t w1, uint32_t w2, double& u_even, double& u_odd) {
+  const uint32_t e_lo = w0 << 4;
+  const uint32_t e_hi = (__builtin_amdgcn_alignbit(w1, w0, 28) & 0x000FFFFFu) | 0x3FF00000u;
+  const uint32_t o_lo = __builtin_amdgcn_alignbit(w2, w1, 12) & 0xFFFFFFF0u;
+  const uint32_t o_hi = __builtin_amdgcn_alignbit(0x3FFu, w2, 12);
+  u_even = bits_to_f64(e_lo, e_hi) - 1.0;
+  u_odd = bits_to_f64(o_lo, o_hi) - 1.0;
+}
+
+// Both output values of the field pair held in words (w0, w1, w2).  For
+// normals, Box-Muller on the pair: r = sqrt(-2 ln(1 - u1)) with u1 the even
+// field's double, and the even and odd positions get r cos(2 pi u2) and
+// r sin(2 pi u2) = r cos(2 pi u2 - pi / 2); 1 - u1 is in (0, 1] and
+// 2 u2 - 1/2 is exact.
+template <Out K>
+__device__ __forceinline__ void pair_values(uint32_t w0, uint32_t w1, uint32_t w2, uint64_t& a, uint64_t& b) {
+  if constexpr (K == Out::U64) {
+    a = ((uint64_t)(w1 & 0xFFFFu) << 32) | w0;
+    b = ((uint64_t)(w2 >> 16) << 32) | __builtin_amdgcn_alignbit(w2, w1, 16);
   } else {
-    uint32_t d[NW];
-    to_ranlux_general(x, d);
-    lds_fields<F64>(d, d, slot);
+    double u1, u2;
+    pair_f64(w0, w1, w2, u1, u2);
+    if constexpr (K == Out::F64) {
+      a = f64_bits(u1);
+      b = f64_bits(u2);
+    } else {
+      const double r = sqrt(-2.0 * log1p(-u1));
+      a = f64_bits(r * cospi(2.0 * u2));
+      b = f64_bits(r * cospi(2.0 * u2 - 0.5));
+    }
   }
 }
 
-template <bool F64>
+// Values per lane of the LDS staging area: the 12 output values of one
+// step, 16-byte aligned.
+constexpr int SLOT_VALUES = FIELDS;
+
+// Convert X (section 2.3) and write the step's 12 output values to this
+// lane's LDS slot.  Per lane, no synchronisation: may run under divergent
+// control flow.
+template <Out K>
+__device__ __forceinline__ void convert_to_lds(const uint32_t (&x)[NW], uint64_t* __restrict__ slot, bool force) {
+  uint32_t d[NW];
+  to_ranlux(x, d, force);
+  ulonglong2* s2 = reinterpret_cast<ulonglong2*>(slot);
+#pragma unroll
+  for (int i = 0; i < FIELDS / 2; ++i) {
+    uint64_t a, b;
+    pair_values<K>(d[3 * i], d[3 * i + 1], d[3 * i + 2], a, b);
+    s2[i] = make_ulonglong2(a, b);
+  }
+}
+
+template <Out K>
 __device__ __forceinline__ uint64_t field_bits(const uint32_t (&d)[NW], int f) {
   const int i = f >> 1;
-  return field_bits_w<F64>(d[3 * i], d[3 * i + 1], d[3 * i + 2], f);
+  uint64_t a, b;
+  pair_values<K>(d[3 * i], d[3 * i + 1], d[3 * i + 2], a, b);
+  return (f & 1) ? b : a;
 }
 
 __device__ __forceinline__ void put_trace(uint64_t* __restrict__ tr, const uint32_t (&x)[NW]) {
@@ -189,36 +223,57 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Store the 12 fields of this lane's block from LDS.
+// 16-byte store; non-temporal (no cache allocation: the output is written
+// once and never read back by the kernel) when NT is set.  Non-temporal
+// stores only pay off for whole 128-byte lines per instruction: partial
+// lines written that way are merged late and cost far more bandwidth.
+template <bool NT>
+__device__ __forceinline__ void store_pair(uint64_t* dst, ulonglong2 v) {
+  typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+  u64x2 w;
+  w.x = v.x;
+  w.y = v.y;
+  if constexpr (NT) {
+    __builtin_nontemporal_store(w, reinterpret_cast<u64x2*>(dst));
+  } else {
+    *reinterpret_cast<u64x2*>(dst) = w;
+  }
+}
+
+// Store the 12 values of this lane's block from LDS.
 //
 // The gs = 2^LGS lanes of a group (gs <= 64, aligned inside the wave) hold
 // consecutive blocks; lane ls holds the group's block ls and has written its
-// 12 fields to its LDS slot (convert_to_lds).  Field f of the group's block m
-// has output index jb + 12 m + f.  After a wave synchronisation lane ls
-// stores the group's entries q gs + ls, q < 12: consecutive lanes write
-// consecutive 8-byte values.  Only indices in [lo, hi) are written, and only
-// by lanes with `active` set.  Called by every lane of the wave.
+// 12 values to its LDS slot (convert_to_lds), so the group's slots hold its
+// 12 gs values in output order.  Value f of the group's block m goes to
+// base[u0 + 12 m + f] when 0 <= u0 + 12 m + f < span.  Only lanes with
+// `active` set store.  Called by every lane of the wave.
+//
+// When the group writes its whole window to a 16-byte aligned address, the
+// values go out as 16-byte pairs: lane ls stores pairs q gs + ls, q < 6, so
+// one store instruction writes 16 gs contiguous bytes per group (whole
+// lines, stored non-temporally, from gs = 8 on).  Otherwise lane ls stores
+// single values q gs + ls, q < 12, with a range check.
 template <int LGS>
 __device__ __forceinline__ void group_store(const uint64_t* __restrict__ stage, uint32_t tid_blk, uint32_t ls,
-                                            int64_t jb, int64_t lo, int64_t hi, bool active,
-                                            uint64_t* __restrict__ out) {
+                                            int64_t u0, uint64_t span, bool active,
+                                            uint64_t* __restrict__ base) {
   constexpr uint32_t gs = 1u << LGS;
   wave_sync();
-  const uint64_t* grp = stage + (size_t)(tid_blk - ls) * FIELDS + ls;
+  const uint64_t* grp = stage + (size_t)(tid_blk - ls) * SLOT_VALUES;
   if (active) {
-    if (jb >= lo && jb + (int64_t)(FIELDS * gs) <= hi) {
-      uint64_t* dst = out + jb + ls;
+    uint64_t* const gdst = base + u0;
+    if (u0 >= 0 && (uint64_t)u0 + FIELDS * gs <= span && (reinterpret_cast<uintptr_t>(gdst) & 15) == 0) {
+      const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(grp);
 #pragma unroll
-      for (int q = 0; q < FIELDS; ++q) dst[q * gs] = grp[q * gs];
+      for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<(gs >= 8)>(gdst + 2 * (q * gs + ls), g2[q * gs + ls]);
     } else {
       // running index (no loop-invariant per-q offsets for the compiler to
-      // keep in registers): u = j - lo, stored when 0 <= u < hi - lo
-      const uint64_t span = (uint64_t)(hi - lo);
-      uint64_t u = (uint64_t)(jb + (int64_t)ls - lo);
-      uint64_t* base = out + lo;
+      // keep in registers): value q goes to base[u], stored when u < span
+      uint64_t u = (uint64_t)(u0 + (int64_t)ls);
 #pragma unroll
       for (int q = 0; q < FIELDS; ++q) {
-        if (u < span) base[u] = grp[q * gs];
+        if (u < span) base[u] = grp[q * gs + ls];
         u += gs;
       }
     }

@@ -63,6 +63,9 @@ def test_invalid_arguments_fail_before_any_device_work(rlx):
     assert lib.rlx_prepare(10, None) == 1
     # overflow of n * count
     assert lib.rlx_generate_f64(ctypes.c_void_p(16), 1 << 40, 1 << 40, ctypes.c_void_p(16), 2048, None) == 1
+    # per-call size limits: n < 2^32 records, count <= 2^35 values
+    assert lib.rlx_generate_f64(ctypes.c_void_p(16), 1 << 32, 1, ctypes.c_void_p(16), 2048, None) == 1
+    assert lib.rlx_generate_u64(ctypes.c_void_p(16), 1, (1 << 35) + 1, ctypes.c_void_p(16), 2048, None) == 1
     # no-ops
     assert lib.rlx_generate_f64(None, 0, 10, None, 2048, None) == 0
     assert lib.rlx_generate_u64(None, 5, 0, None, 2048, None) == 0
