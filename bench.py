@@ -37,7 +37,7 @@ DRAWS = 4096
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
 VALU_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (full-rate 32-bit ops)
 MADS_PER_DOUBLE = 27              # 18 x 18 32-bit multiply-adds per step / 12 doubles
-KERNEL_SOURCES = ("paper_2106_02504_amd/csrc/rlx.hip", "paper_2106_02504_amd/csrc/rlx_arith.hpp",
+KERNEL_SOURCES = ("paper_2106_02504_amd/csrc/rlx.hip", "include/rlx_arith.hpp",
                   "paper_2106_02504_amd/csrc/rlx_device.hpp")
 
 

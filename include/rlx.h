@@ -99,6 +99,35 @@ const char *rlx_version(void);
  * windows). */
 int rlx_prepare(uint32_t p, void *stream);
 
+/* Layout of the device tables of one luxury level p (section 2.4; words are
+ * 32-bit, 18 per 576-bit number, least significant first):
+ *   windows[(i * RLX_TAB_COLS + j) * 18 .. + 17] = A_p^(j 16^i) mod m,
+ *     i < RLX_TAB_ROWS, j < RLX_TAB_COLS.  Rows 0..15 are the 4-bit windows
+ *     of a skip by k < 2^64 steps; rows RLX_SEED_ROW0.. those of a seed's
+ *     exponent 2^96 id.
+ *   folded[(g * 21 + j) * 18 .. + 17] = A_p^(2^g) 2^(o_j) mod m, g <
+ *     RLX_FOLD_G, j < 21, o_j the limb offsets 0, 28, ..., 280, 307, ..., 550
+ *     (ten 28-bit, ten 27-bit and one 26-bit limb): the folded multiplier of
+ *     2^g generator steps, X <- A_p^(2^g) X = sum_j limb_j(X) C_g[j]. */
+#define RLX_TAB_ROWS 40
+#define RLX_TAB_COLS 16
+#define RLX_SEED_ROW0 24
+#define RLX_FOLD_G 64
+
+typedef struct rlx_engine_tables {
+    const uint32_t *windows;  /* RLX_TAB_ROWS * RLX_TAB_COLS * 18 words */
+    const uint32_t *folded;   /* RLX_FOLD_G * 21 * 18 words */
+    uint32_t p;               /* luxury level */
+    uint32_t reserved;
+} rlx_engine_tables;
+
+/* Addresses of the tables of level p on the current device, for kernels
+ * that run the device-side engine of rlx_engine.h (the paper's GPU use, one
+ * generator per thread, section 4.2).  Builds them as rlx_prepare() does.
+ * The memory is owned by the library, read-only for kernels, and valid until
+ * the process ends.  RLX_EINVAL for p < 24 or out == NULL. */
+int rlx_get_tables(uint32_t p, rlx_engine_tables *out, void *stream);
+
 /* Seeding (section 2.4).  states[i] <- stream record of seed id
  * ids[i] (or id0 + i when ids == NULL) at luxury level p:
  *   x = A_p^(2^96 id) mod m applied to X = 1, pos = 0, p = p.
@@ -290,6 +319,19 @@ int rlx_test_pow(const uint64_t *base, const uint64_t *exps, uint64_t *out,
  * RANLUX carry bit c = X - D + floor(D / 2^336). */
 int rlx_test_to_ranlux(const uint64_t *x, uint64_t *d, uint32_t *carry,
                        uint64_t n, void *stream);
+
+/* Test-only: the device-side engine of rlx_engine.h driven from a kernel
+ * written as user code, one thread per record:
+ *   mode 0  load the record, draw `count` doubles into out[i * count + j]
+ *           (rlx_engine_next_f64), store the record;
+ *   mode 1  as 0 after seeding record i with id i (rlx_engine_seed);
+ *   mode 2  as 0 after skipping i generator steps (rlx_engine_skip);
+ *   mode 3  as 0 with rlx_engine_next_normal;
+ *   mode 4  as 0 with rlx_engine_next_u48 (bits in out);
+ *   mode 5  out[i] = the sum, in draw order, of `count` doubles (the
+ *           paper's GPU benchmark, section 4.2); store the record. */
+int rlx_test_engine(rlx_state *states, uint64_t n, uint64_t count,
+                    double *out, uint32_t mode, uint32_t p, void *stream);
 
 /* rlx_generate_u64 with every rare-case branch of the step and the
  * conversion taken by all lanes (the exact general code), so that the general

@@ -1,4 +1,5 @@
-// rlx_arith.hpp -- 576-bit modular arithmetic of RANLUX++ for gfx950.
+// rlx_arith.hpp -- 576-bit modular arithmetic of RANLUX++ for gfx950 (used by
+// librlx.so and by the device-side engine of rlx_engine.h).
 //
 // Numbers below 2^576 are held as eighteen 32-bit words, least significant
 // first.  The modulus is m = 2^576 - 2^240 + 1 (paper, section 2.2).  Two
@@ -230,6 +231,26 @@ RLX_HD void unpack_limbs(const uint32_t (&w)[NW], uint32_t (&l)[NL]) {
   }
 }
 
+// Row-offset barrier for the generator step: an empty asm that claims to
+// modify the (scalar) offset using a word `dep` of the previous row, so the
+// table load using the offset cannot move above the arrival of that row.
+struct SgprBarrier {
+  __device__ __forceinline__ uint32_t operator()(uint32_t v, uint32_t dep) const {
+    asm volatile("" : "+s"(v) : "s"(dep));
+    return v;
+  }
+};
+
+// Table words seen through the constant address space: the compiler may
+// then read them with scalar loads (it treats the memory as unchanging for
+// the whole launch), even when the table address itself was loaded from
+// device memory.
+typedef const __attribute__((address_space(4))) uint32_t const_u32;
+
+__device__ __forceinline__ const_u32* constant_table(const uint32_t* p) {
+  return (const_u32*)p;
+}
+
 // Identity map of a table offset; kernels pass one that hides the offset
 // from the optimiser (see step()).
 struct Plain {
@@ -380,6 +401,26 @@ RLX_HD uint32_t ranlux_carry(const uint32_t (&x)[NW], const uint32_t (&d)[NW]) {
   // value is known to be that small.
   uint32_t lo = x[0] - d[0] + window32(d, 10, 16);
   return lo;
+}
+
+// X = D - floor(D / 2^336) + c: the inverse of the conversion (D, c) =
+// (to_ranlux(X), ranlux_carry(X, D)) on canonical X (the relation behind
+// both is 2^576 = m + 2^240 - 1, section 2.3).  Returns false when the
+// result leaves [0, 2^576) (a borrow or a carry out), which happens only for
+// pairs (D, c) that no canonical X exports to; the caller still has to check
+// X < m and the round trip when (D, c) comes from outside.
+RLX_HD bool from_ranlux(const uint32_t (&d)[NW], uint32_t c, uint32_t (&x)[NW]) {
+  uint32_t br = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) x[k] = subb(d[k], window32(d, 10 + k, 16), br);
+  uint32_t cy = c > 1u ? 2u : c;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const uint64_t v = (uint64_t)x[k] + cy;
+    x[k] = (uint32_t)v;
+    cy = (uint32_t)(v >> 32);
+  }
+  return br == 0 && cy == 0;
 }
 
 // ---------------------------------------------------------------------------

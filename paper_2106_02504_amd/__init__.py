@@ -25,6 +25,7 @@ import torch  # load torch's HIP runtime first: librlx.so binds to the same one
 __all__ = [
     "RlxError", "lib", "new_states", "prepare", "init_streams", "skip",
     "generate_f64", "generate_u64", "generate_normal_f64", "generate_f64_trace", "check_errors",
+    "EngineTables", "get_tables", "test_engine",
     "set_lanes_per_stream", "lanes_per_stream", "skip_values", "export_ranlux", "import_ranlux", "REQUEST_DTYPE", "requests_array", "Plan", "plan_dry_run",
     "constants", "test_mulmod", "test_pow", "test_to_ranlux",
     "test_generate_u64_general", "STATE_WORDS",
@@ -51,6 +52,8 @@ _SIGS = {
     "rlx_generate_f64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_u64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_normal_f64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
+    "rlx_get_tables": (_int, [_u32, _vp, _vp]),
+    "rlx_test_engine": (_int, [_vp, _u64, _u64, _vp, _u32, _u32, _vp]),
     "rlx_generate_f64_trace": (_int, [_vp, _u64, _u64, _vp, _vp, _u64, _u32, _vp]),
     "rlx_check_errors": (_int, [_vp, ctypes.POINTER(_u32)]),
     "rlx_set_lanes_per_stream": (_int, [_u32]),
@@ -237,6 +240,38 @@ def generate_normal_f64(states: torch.Tensor, count: int, p: int, out: torch.Ten
         _check(lib().rlx_generate_normal_f64(states.data_ptr(), n, count, out.data_ptr(), p, _stream()),
                "rlx_generate_normal_f64")
     return out
+
+
+class EngineTables(ctypes.Structure):
+    """rlx_engine_tables: device addresses of a luxury level's tables, to be
+    passed by value to kernels that use the device-side engine."""
+    _fields_ = [("windows", ctypes.c_void_p), ("folded", ctypes.c_void_p),
+                ("p", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+def get_tables(p: int, device=None) -> EngineTables:
+    """The tables of level p on `device` (built on first use)."""
+    t = EngineTables()
+    with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
+        _check(lib().rlx_get_tables(p, ctypes.byref(t), _stream()), "rlx_get_tables")
+    return t
+
+
+ENGINE_MODES = {"f64": 0, "seed": 1, "skip": 2, "normal": 3, "u48": 4, "sum": 5}
+
+
+def test_engine(states: torch.Tensor, count: int, p: int, mode: str) -> torch.Tensor:
+    """Test hook: run the device-side engine (rlx_engine.h) from a kernel
+    written as user code, one thread per record; returns [n, count] values
+    (float64, or the u48 bits as int64 for mode "u48"; [n] sums for "sum")."""
+    n = _need_states(states)
+    m = ENGINE_MODES[mode]
+    shape = (n,) if mode == "sum" else (n, count)
+    out = torch.empty(shape, dtype=torch.float64, device=states.device)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_test_engine(states.data_ptr(), n, count, out.data_ptr(), m, p, _stream()),
+               "rlx_test_engine")
+    return out.view(torch.int64) if mode == "u48" else out
 
 
 def generate_f64_trace(states: torch.Tensor, count: int, p: int):

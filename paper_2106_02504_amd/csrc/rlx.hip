@@ -286,18 +286,8 @@ __global__ __launch_bounds__(BLOCK) void k_import(rlx_state* __restrict__ st, ui
     atomicOr(err, RLX_ERR_BAD_POS);
     return;
   }
-  // X = D - (D >> 336) + c; D >> 336 = window of D from word 10, bit 16
-  uint32_t br = 0;
-#pragma unroll
-  for (int k = 0; k < NW; ++k) x[k] = subb(d[k], window32(d, 10 + k, 16), br);
-  uint32_t cy = c > 1u ? 2u : c;  // a carry other than 0/1 fails the round trip below
-#pragma unroll
-  for (int k = 0; k < NW; ++k) {
-    const uint64_t v = (uint64_t)x[k] + cy;
-    x[k] = (uint32_t)v;
-    cy = (uint32_t)(v >> 32);
-  }
-  bool ok = (br == 0) && (cy == 0) && !geq_m(x);
+  // a carry other than 0/1 fails in from_ranlux or in the round trip below
+  bool ok = from_ranlux(d, c, x) && !geq_m(x);
   if (ok) {
     uint32_t d2[NW];
     to_ranlux(x, d2, false);
@@ -552,6 +542,18 @@ int rlx_prepare(uint32_t p, void* stream) {
   if (rc) return rc;
   uint32_t* err;
   return error_word(as_stream(stream), &err);
+}
+
+int rlx_get_tables(uint32_t p, rlx_engine_tables* out, void* stream) {
+  if (!out || !valid_p(p)) return RLX_EINVAL;
+  Tables t;
+  int rc = tables(p, as_stream(stream), &t);
+  if (rc) return rc;
+  out->windows = t.T;
+  out->folded = t.C;
+  out->p = p;
+  out->reserved = 0;
+  return RLX_OK;
 }
 
 int rlx_init_streams(rlx_state* states, uint64_t n, const uint64_t* ids, uint64_t id0, uint32_t p,

@@ -15,11 +15,11 @@ namespace rlx {
 //             k < 2^64 steps, rows 24..39 serve seeds (exponent 2^96 id).
 //   C[g][j] = A_p^(2^g) 2^(o_j) mod m, g < 64, j < 21 (o_j = limb_offset(j)): the folded
 //             multiplier of a step by 2^g generator steps (see step()).
-constexpr int TAB_ROWS = 40;
-constexpr int TAB_COLS = 16;
-constexpr int SEED_ROW0 = 24;  // 2^96 = 16^24
+constexpr int TAB_ROWS = RLX_TAB_ROWS;
+constexpr int TAB_COLS = RLX_TAB_COLS;
+constexpr int SEED_ROW0 = RLX_SEED_ROW0;  // 2^96 = 16^24
 constexpr size_t TAB_WORDS = (size_t)TAB_ROWS * TAB_COLS * NW;
-constexpr int FOLD_G = 64;
+constexpr int FOLD_G = RLX_FOLD_G;
 constexpr size_t FOLD_ROW_WORDS = (size_t)NL * NW;  // one folded multiplier
 constexpr size_t FOLD_WORDS = (size_t)FOLD_G * FOLD_ROW_WORDS;
 constexpr int BLOCK = 256;
@@ -88,26 +88,6 @@ __device__ __forceinline__ uint32_t check_record(const uint32_t (&x)[NW], uint32
   if (pos > 11) bad |= RLX_ERR_BAD_POS;
   if (geq_m(x)) bad |= RLX_ERR_BAD_X;
   return bad;
-}
-
-// Row-offset barrier for the generator step: an empty asm that claims to
-// modify the (scalar) offset using a word `dep` of the previous row, so the
-// table load using the offset cannot move above the arrival of that row.
-struct SgprBarrier {
-  __device__ __forceinline__ uint32_t operator()(uint32_t v, uint32_t dep) const {
-    asm volatile("" : "+s"(v) : "s"(dep));
-    return v;
-  }
-};
-
-// Table words seen through the constant address space: the compiler may
-// then read them with scalar loads (it treats the memory as unchanging for
-// the whole launch), even when the table address itself was loaded from
-// device memory.
-typedef const __attribute__((address_space(4))) uint32_t const_u32;
-
-__device__ __forceinline__ const_u32* constant_table(const uint32_t* p) {
-  return (const_u32*)p;
 }
 
 __device__ __forceinline__ void mulmod_inplace(uint32_t (&x)[NW], const uint32_t (&y)[NW]) {

@@ -1,4 +1,4 @@
-"""The library's 576-bit arithmetic (csrc/rlx_arith.hpp) compiled for the
+"""The library's 576-bit arithmetic (include/rlx_arith.hpp) compiled for the
 host and checked against the oracle on the CPU: generic mulmod, the folded
 constant-multiplier step (fast path and forced general path), the conversion
 to RANLUX numbers (both paths), the carry and the fields, on random operands
@@ -44,7 +44,7 @@ def harness(tmp_path_factory):
     d = tmp_path_factory.mktemp("host_arith")
     exe = str(d / "harness")
     src = os.path.join(ROOT, "tests", "host_arith", "harness.hip")
-    inc = os.path.join(ROOT, "paper_2106_02504_amd", "csrc")
+    inc = os.path.join(ROOT, "include")
     subprocess.run([HIPCC, "--offload-arch=gfx950", "-O1", "-std=c++17", "-I", inc, "-I",
                     os.path.join(ROOT, "include"), "-o", exe, src], check=True, capture_output=True)
     return exe

@@ -63,6 +63,10 @@ def test_invalid_arguments_fail_before_any_device_work(rlx):
     assert lib.rlx_prepare(10, None) == 1
     # overflow of n * count
     assert lib.rlx_generate_f64(ctypes.c_void_p(16), 1 << 40, 1 << 40, ctypes.c_void_p(16), 2048, None) == 1
+    # table accessor: bad level or NULL output
+    assert lib.rlx_get_tables(23, ctypes.c_void_p(16), None) == 1
+    assert lib.rlx_get_tables(2048, None, None) == 1
+    assert lib.rlx_test_engine(ctypes.c_void_p(16), 5, 10, ctypes.c_void_p(16), 9, 2048, None) == 1
     # per-call size limits: n < 2^32 records, count <= 2^35 values
     assert lib.rlx_generate_f64(ctypes.c_void_p(16), 1 << 32, 1, ctypes.c_void_p(16), 2048, None) == 1
     assert lib.rlx_generate_u64(ctypes.c_void_p(16), 1, (1 << 35) + 1, ctypes.c_void_p(16), 2048, None) == 1
