@@ -217,6 +217,41 @@ def serve_leg(rlx, torch, np, dev, plain_rate, args):
     return res
 
 
+def engine_leg(rlx, torch, dev, args):
+    """The paper's GPU benchmark form (section 4.2): 1024 x 128 threads, each
+    summing 10^6 doubles from its own generator, here through the device-side
+    engine.  Uniform start (every stream at position 0) against staggered
+    start (stream i at position i, so threads advance at different times)."""
+    n = 1024 * 128
+    draws = args.engine_draws
+    res = {"threads": n, "draws_per_thread": draws, "p": P,
+           "paper_context": "RTX 2070 SUPER: 11.8 s uniform, more than 80 s staggered (10^6 draws)"}
+    for name, stagger in (("uniform", False), ("staggered", True)):
+        st = rlx.new_states(n, device=dev)
+
+        def reset():
+            rlx.init_streams(st, P, id0=0)
+            if stagger:
+                rlx.skip_values(st, torch.arange(n, dtype=torch.int64, device=dev), P)
+        reset()
+        rlx.test_engine(st, 1000, P, "sum")  # warm-up
+        times = []
+        for _ in range(3):
+            reset()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rlx.test_engine(st, draws, P, "sum")
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        t = min(times)
+        res[name] = {"seconds": t, "doubles_per_s": n * draws / t}
+        del st
+    res["staggered_over_uniform"] = res["staggered"]["seconds"] / res["uniform"]["seconds"]
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,8 +259,11 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=8192)
-    ap.add_argument("--legs", default="u64,single,skip,batch,serve", help="extra legs to time (comma list or 'none')")
+    ap.add_argument("--legs", default="u64,normal,single,skip,engine,batch,serve",
+                    help="extra legs to time (comma list or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--engine-draws", type=int, default=10 ** 6,
+                    help="draws per thread in the device-engine leg (the paper's 10^6)")
     ap.add_argument("--lanes", type=int, default=0, help="force lanes per stream (0 = library's pick)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
@@ -345,6 +383,21 @@ def main() -> int:
         legs["skip"] = {"value": n3 / dt, "unit": "states/s", "ms_per_step": dt * 1e3,
                         "workload": "2^20 states, offsets log-uniform in [1, 2^64) steps"}
         del st3, offs
+
+    if "normal" in wanted:
+        outn = torch.empty((N_STREAMS, DRAWS), dtype=torch.float64, device=dev)
+
+        def step_n():
+            rlx.init_streams(st, P, id0=0)
+            rlx.generate_normal_f64(st, DRAWS, P, out=outn)
+        dt = timed(step_n, stream, max(5, args.steps // 5), 2, torch)
+        flat = outn.view(-1)
+        legs["normal"] = {"value": total / dt, "unit": "normals/s", "ms_per_step": dt * 1e3,
+                          "mean": float(flat.mean()), "var": float(flat.var()),
+                          "workload": "many-streams shape, Box-Muller on field pairs"}
+        del outn, flat
+    if "engine" in wanted:
+        legs["engine"] = engine_leg(rlx, torch, dev, args)
 
     if "batch" in wanted:
         del out
