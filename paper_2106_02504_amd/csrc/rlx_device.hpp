@@ -229,11 +229,16 @@ __device__ __forceinline__ void store_pair(uint64_t* dst, ulonglong2 v) {
 // base[u0 + 12 m + f] when 0 <= u0 + 12 m + f < span.  Only lanes with
 // `active` set store.  Called by every lane of the wave.
 //
-// When the group writes its whole window to a 16-byte aligned address, the
-// values go out as 16-byte pairs: lane ls stores pairs q gs + ls, q < 6, so
-// one store instruction writes 16 gs contiguous bytes per group (whole
-// lines, stored non-temporally, from gs = 8 on).  Otherwise lane ls stores
-// single values q gs + ls, q < 12, with a range check.
+// When the group writes its whole window, the values go out as 16-byte
+// pairs: lane ls stores pairs q gs + ls, q < 6, so one store instruction
+// writes 16 gs contiguous bytes per group.  If the window starts 8 bytes off
+// a 16-byte boundary (an odd output offset), the pairs are shifted by one
+// value: lane 0 also stores value 0 alone and lane gs - 1 stores the last
+// value alone in place of its last pair.  The stores are non-temporal only
+// when a group's run is whole 128-byte lines (from gs = 8 on, on a line
+// boundary): partial lines written that way are merged late and cost far
+// more bandwidth.  Windows cut by the range take single range-checked
+// stores.
 template <int LGS>
 __device__ __forceinline__ void group_store(const uint64_t* __restrict__ stage, uint32_t tid_blk, uint32_t ls,
                                             int64_t u0, uint64_t span, bool active,
@@ -241,12 +246,39 @@ __device__ __forceinline__ void group_store(const uint64_t* __restrict__ stage, 
   constexpr uint32_t gs = 1u << LGS;
   wave_sync();
   const uint64_t* grp = stage + (size_t)(tid_blk - ls) * SLOT_VALUES;
-  if (active) {
-    uint64_t* const gdst = base + u0;
-    if (u0 >= 0 && (uint64_t)u0 + FIELDS * gs <= span && (reinterpret_cast<uintptr_t>(gdst) & 15) == 0) {
-      const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(grp);
+  uint64_t* const gdst = base + u0;
+  const uintptr_t a = reinterpret_cast<uintptr_t>(gdst);
+  const bool whole = u0 >= 0 && (uint64_t)u0 + FIELDS * gs <= span;
+  if (gs >= 8 && __all(active && whole && (a & 127) == 0)) {
+    // the common case of a whole wave on line boundaries, as one branch
+    const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(grp);
 #pragma unroll
-      for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<(gs >= 8)>(gdst + 2 * (q * gs + ls), g2[q * gs + ls]);
+    for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<true>(gdst + 2 * (q * gs + ls), g2[q * gs + ls]);
+  } else if (active) {
+    if (whole) {
+      if ((a & 15) == 0) {
+        const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(grp);
+        if (gs >= 8 && (a & 127) == 0) {
+#pragma unroll
+          for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<true>(gdst + 2 * (q * gs + ls), g2[q * gs + ls]);
+        } else {
+#pragma unroll
+          for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<false>(gdst + 2 * (q * gs + ls), g2[q * gs + ls]);
+        }
+      } else {
+        // pairs k = (values 2k + 1, 2k + 2), k < 6 gs - 1, at 16-byte
+        // aligned gdst + 2k + 1
+        if (ls == 0) gdst[0] = grp[0];
+#pragma unroll
+        for (uint32_t q = 0; q < FIELDS / 2; ++q) {
+          const uint32_t k = q * gs + ls;
+          if (q + 1 < FIELDS / 2 || ls + 1 < gs) {
+            store_pair<false>(gdst + 2 * k + 1, make_ulonglong2(grp[2 * k + 1], grp[2 * k + 2]));
+          } else {
+            gdst[FIELDS * gs - 1] = grp[FIELDS * gs - 1];
+          }
+        }
+      }
     } else {
       // running index (no loop-invariant per-q offsets for the compiler to
       // keep in registers): value q goes to base[u], stored when u < span
