@@ -213,6 +213,12 @@ def serve_leg(rlx, torch, np, dev, plain_rate, args):
         summ = st.summary()
         summ.pop("starts", None)
         res["runs"].append(dict(load=frac, rate_per_s=lam, **summ))
+    # capacity: the same requests all arriving at once
+    reqs = workloads.serve_requests(args.serve_requests, 1.0)
+    st = srv.run([0.0] * len(reqs), [r.stream_id for r in reqs], [r.count for r in reqs])
+    summ = st.summary()
+    res["capacity"] = {"doubles_per_s": summ["doubles_per_s"], "fraction_of_plain": summ["doubles_per_s"] / plain_rate,
+                       "batches": summ["batches"], "makespan_s": summ["makespan_s"]}
     srv.close()
     return res
 

@@ -20,8 +20,8 @@ import torch
 
 from . import Plan
 
-DEFAULT_LANES = (4, 8, 16, 32)
-DEFAULT_SEG_BLOCKS = (512, 2048, 8192)
+DEFAULT_LANES = (8, 16, 32)
+DEFAULT_SEG_BLOCKS = (512, 1024, 2048, 4096, 8192)
 
 
 def cache_path() -> str:

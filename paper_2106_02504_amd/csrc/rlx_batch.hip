@@ -174,8 +174,15 @@ struct Planned {
   uint64_t total = 0;
 };
 
+// Segments are laid out level by level; inside a level, the full segments
+// (seg_blocks steps) in request order, then the partial ones (at most one per
+// request) by decreasing length.  Items take 64/G consecutive segments of one
+// level and run longest first.  Only the partial segments and the items that
+// hold them are sorted, so planning is linear in the number of segments.
 int plan_requests(const rlx_request* reqs, uint64_t n, uint32_t lg, uint64_t seg_blocks, Planned* out) {
   Planned pl;
+  std::vector<uint32_t> slot_of(n, 0);
+  std::vector<uint64_t> full_n, part_n;  // per level
   for (uint64_t r = 0; r < n; ++r) {
     const rlx_request& q = reqs[r];
     if (q.reserved != 0 || !valid_p(q.p)) return RLX_EINVAL;
@@ -187,42 +194,72 @@ int plan_requests(const rlx_request* reqs, uint64_t n, uint32_t lg, uint64_t seg
     if (slot == pl.ps.size()) {
       if (pl.ps.size() == MAX_LEVELS) return RLX_EINVAL;
       pl.ps.push_back(q.p);
+      full_n.push_back(0);
+      part_n.push_back(0);
     }
+    slot_of[r] = slot;
+    const uint64_t nb = (q.start % FIELDS + q.count + FIELDS - 1) / FIELDS;
+    full_n[slot] += nb / seg_blocks;
+    part_n[slot] += (nb % seg_blocks) != 0;
+    pl.total += q.count;
+  }
+  const size_t levels = pl.ps.size();
+  std::vector<uint64_t> full_at(levels), part_at(levels), part_end(levels);
+  uint64_t total_segs = 0;
+  for (size_t k = 0; k < levels; ++k) {
+    full_at[k] = total_segs;
+    part_at[k] = total_segs + full_n[k];
+    total_segs += full_n[k] + part_n[k];
+    part_end[k] = total_segs;
+  }
+  if (total_segs > 0xFFFFFFFFull) return RLX_EINVAL;
+  pl.segs.resize(total_segs);
+  for (uint64_t r = 0; r < n; ++r) {
+    const rlx_request& q = reqs[r];
+    if (q.count == 0) continue;
+    const uint32_t slot = slot_of[r];
     const uint64_t b0 = q.start / FIELDS;
     const uint64_t f0 = q.start % FIELDS;
     const uint64_t nb = (f0 + q.count + FIELDS - 1) / FIELDS;
     for (uint64_t k = 0; k * seg_blocks < nb; ++k) {
-      Segment s;
-      s.state = q.state;
-      s.block = b0 + k * seg_blocks;
-      s.jbase = (int64_t)q.out_offset + (int64_t)(FIELDS * k * seg_blocks) - (int64_t)f0;
-      s.lo = (int64_t)q.out_offset;
-      s.hi = (int64_t)(q.out_offset + q.count);
-      s.nblocks = (uint32_t)std::min<uint64_t>(seg_blocks, nb - k * seg_blocks);
-      s.slot = slot;
-      pl.segs.push_back(s);
+      const uint64_t len = std::min<uint64_t>(seg_blocks, nb - k * seg_blocks);
+      Segment& sg = pl.segs[len == seg_blocks ? full_at[slot]++ : part_at[slot]++];
+      sg.state = q.state;
+      sg.block = b0 + k * seg_blocks;
+      sg.jbase = (int64_t)q.out_offset + (int64_t)(FIELDS * k * seg_blocks) - (int64_t)f0;
+      sg.lo = (int64_t)q.out_offset;
+      sg.hi = (int64_t)(q.out_offset + q.count);
+      sg.nblocks = (uint32_t)len;
+      sg.slot = slot;
     }
-    pl.total += q.count;
   }
-  if (pl.segs.size() > 0xFFFFFFFFull) return RLX_EINVAL;
-  std::stable_sort(pl.segs.begin(), pl.segs.end(), [](const Segment& a, const Segment& b) {
-    return a.slot != b.slot ? a.slot < b.slot : a.nblocks > b.nblocks;
-  });
+  for (size_t k = 0; k < levels; ++k) {
+    std::stable_sort(pl.segs.begin() + (part_end[k] - part_n[k]), pl.segs.begin() + part_end[k],
+                     [](const Segment& a, const Segment& b) { return a.nblocks > b.nblocks; });
+  }
+  // items: those that start with a full segment (cost seg_blocks) first, in
+  // level order, then the rest by decreasing cost
   const uint32_t per_item = WAVE >> lg;  // segments per 64-lane item
-  for (size_t i = 0; i < pl.segs.size();) {
-    Item it;
-    it.seg0 = (uint32_t)i;
-    it.slot = pl.segs[i].slot;
-    it.cost = pl.segs[i].nblocks;
-    uint32_t k = 0;
-    while (k < per_item && i < pl.segs.size() && pl.segs[i].slot == it.slot) {
-      ++k;
-      ++i;
+  std::vector<Item> rest;
+  pl.items.reserve(total_segs / per_item + 2 * levels);
+  for (size_t k = 0, i = 0; k < levels; ++k) {
+    const uint64_t end = part_end[k];
+    while (i < end) {
+      Item it;
+      it.seg0 = (uint32_t)i;
+      it.slot = (uint32_t)k;
+      it.cost = pl.segs[i].nblocks;
+      it.nseg = (uint32_t)std::min<uint64_t>(per_item, end - i);
+      i += it.nseg;
+      if (it.cost == seg_blocks) {
+        pl.items.push_back(it);
+      } else {
+        rest.push_back(it);
+      }
     }
-    it.nseg = k;
-    pl.items.push_back(it);
   }
-  std::stable_sort(pl.items.begin(), pl.items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  std::stable_sort(rest.begin(), rest.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  pl.items.insert(pl.items.end(), rest.begin(), rest.end());
   *out = std::move(pl);
   return RLX_OK;
 }
