@@ -126,17 +126,16 @@ __device__ __forceinline__ uint64_t f64_bits(double v) {
 }
 
 // The doubles of the field pair held in words (w0, w1, w2) (fields 2i and
-// 2i + 1 of a step: bits 0..47 and 48..95 of the three words), each v 2^-48
-// formed exactly as the bits of 1 + v 2^-48 minus 1.0.  The mantissa bits
-// are v << 4; for the odd field that is (w2:w1) >> 12 with the low four bits
-// cleared, and its exponent word is (0x3FF:w2) >> 12.
+// 2i + 1 of a step: bits 0..47 and 48..95 of the three words), each v 2^-48.
+// With v < 2^48, the bits 0x403 << 52 | v are the double 16 + v 2^-48 (v
+// fills the low 48 mantissa bits as it is, no shift), and subtracting 16 is
+// exact (both operands lie in [16, 32)).
 __device__ __forceinline__ void pair_f64(uint32_t w0, uint32_t w1, uint32_t w2, double& u_even, double& u_odd) {
-  const uint32_t e_lo = w0 << 4;
-  const uint32_t e_hi = (__builtin_amdgcn_alignbit(w1, w0, 28) & 0x000FFFFFu) | 0x3FF00000u;
-  const uint32_t o_lo = __builtin_amdgcn_alignbit(w2, w1, 12) & 0xFFFFFFF0u;
-  const uint32_t o_hi = __builtin_amdgcn_alignbit(0x3FFu, w2, 12);
-  u_even = bits_to_f64(e_lo, e_hi) - 1.0;
-  u_odd = bits_to_f64(o_lo, o_hi) - 1.0;
+  const uint32_t e_hi = (w1 & 0xFFFFu) | 0x40300000u;
+  const uint32_t o_lo = __builtin_amdgcn_alignbit(w2, w1, 16);
+  const uint32_t o_hi = __builtin_amdgcn_alignbit(0x4030u, w2, 16);
+  u_even = bits_to_f64(w0, e_hi) - 16.0;
+  u_odd = bits_to_f64(o_lo, o_hi) - 16.0;
 }
 
 // Both output values of the field pair held in words (w0, w1, w2).  For
@@ -167,19 +166,36 @@ __device__ __forceinline__ void pair_values(uint32_t w0, uint32_t w1, uint32_t w
 // step, 16-byte aligned.
 constexpr int SLOT_VALUES = FIELDS;
 
-// Convert X (section 2.3) and write the step's 12 output values to this
-// lane's LDS slot.  Per lane, no synchronisation: may run under divergent
-// control flow.
-template <Out K>
-__device__ __forceinline__ void convert_to_lds(const uint32_t (&x)[NW], uint64_t* __restrict__ slot, bool force) {
-  uint32_t d[NW];
-  to_ranlux(x, d, force);
+// Write the 12 output values of a step to an LDS slot from D's words 0..8
+// in `lo` and 9..17 in `hi` (after the fast conversion hi is X itself).
+template <Out K, int NLO>
+__device__ __forceinline__ void write_values(const uint32_t (&lo)[NLO], const uint32_t (&hi)[NW],
+                                             uint64_t* __restrict__ slot) {
   ulonglong2* s2 = reinterpret_cast<ulonglong2*>(slot);
 #pragma unroll
   for (int i = 0; i < FIELDS / 2; ++i) {
+    const uint32_t w0 = 3 * i < 9 ? lo[(3 * i) % NLO] : hi[3 * i];
+    const uint32_t w1 = 3 * i + 1 < 9 ? lo[(3 * i + 1) % NLO] : hi[3 * i + 1];
+    const uint32_t w2 = 3 * i + 2 < 9 ? lo[(3 * i + 2) % NLO] : hi[3 * i + 2];
     uint64_t a, b;
-    pair_values<K>(d[3 * i], d[3 * i + 1], d[3 * i + 2], a, b);
+    pair_values<K>(w0, w1, w2, a, b);
     s2[i] = make_ulonglong2(a, b);
+  }
+}
+
+// Convert X (section 2.3) and write the step's 12 output values to this
+// lane's LDS slot.  The two branches write separately, so the common one
+// reads X's words where they are instead of merging copies.  Per lane, no
+// synchronisation: may run under divergent control flow.
+template <Out K>
+__device__ __forceinline__ void convert_to_lds(const uint32_t (&x)[NW], uint64_t* __restrict__ slot, bool force) {
+  uint32_t dlo[9];
+  if (!to_ranlux_fast(x, dlo, force)) {
+    write_values<K>(dlo, x, slot);
+  } else {
+    uint32_t d[NW];
+    to_ranlux_general(x, d);
+    write_values<K>(d, d, slot);
   }
 }
 
