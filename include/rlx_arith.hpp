@@ -134,26 +134,47 @@ RLX_HD void fold_word_general(uint32_t (&x)[NW], uint32_t h) {
 // ---------------------------------------------------------------------------
 // generic multiplication modulo m (sections 2.1, 2.2)
 
-// p = x * y, 36 words.  Column sums of up to 18 products of 64 bits are
-// accumulated in 64 bits plus a carry count.
+// p = x * y, 36 words.  Both factors are split into 21 digits of 28 bits
+// (the top one 16 bits).  A digit product is below 2^56 and a column holds
+// at most 21 of them, so a column plus the carry from below stays under
+// 2^61: each column is one chain of multiply-adds into a 64-bit accumulator
+// that starts from the previous column's carry, with no carry handling
+// inside the chain.  The 41 product digits (28 bits each) are then packed
+// into 32-bit words.
+constexpr int GD = 21;  // 28-bit digits of a 576-bit number
+
+template <int N>
+RLX_HD void digits28(const uint32_t (&w)[N], uint32_t (&d)[GD]) {
+#pragma unroll
+  for (int j = 0; j < GD; ++j) d[j] = window32(w, (28 * j) >> 5, (28 * j) & 31) & 0x0FFFFFFFu;
+}
+
 RLX_HD void mul576(const uint32_t (&x)[NW], const uint32_t (&y)[NW], uint32_t (&p)[2 * NW]) {
+  uint32_t a[GD], b[GD];
+  digits28(x, a);
+  digits28(y, b);
+  uint32_t d[2 * GD];  // product digits, base 2^28
   uint64_t acc = 0;
-  uint32_t top = 0;
 #pragma unroll
-  for (int k = 0; k < 2 * NW - 1; ++k) {
-    const int ilo = k < NW ? 0 : k - NW + 1;
-    const int ihi = k < NW ? k : NW - 1;
+  for (int c = 0; c < 2 * GD - 1; ++c) {
+    const int ilo = c < GD ? 0 : c - GD + 1;
+    const int ihi = c < GD ? c : GD - 1;
 #pragma unroll
-    for (int i = ilo; i <= ihi; ++i) {
-      uint64_t t = (uint64_t)x[i] * y[k - i];
-      acc += t;
-      top += (acc < t) ? 1u : 0u;
-    }
-    p[k] = (uint32_t)acc;
-    acc = (acc >> 32) | ((uint64_t)top << 32);
-    top = 0;
+    for (int i = ilo; i <= ihi; ++i) acc += (uint64_t)a[i] * b[c - i];
+    d[c] = (uint32_t)acc & 0x0FFFFFFFu;
+    acc >>= 28;
   }
-  p[2 * NW - 1] = (uint32_t)acc;
+  d[2 * GD - 1] = (uint32_t)acc;
+  // word k = bits [32 k, 32 k + 32): digits floor(32 k / 28) and up
+#pragma unroll
+  for (int k = 0; k < 2 * NW; ++k) {
+    const int c = (32 * k) / 28;
+    const int s = (32 * k) % 28;
+    uint32_t v = d[c] >> s;
+    if (c + 1 < 2 * GD) v |= d[c + 1] << (28 - s);
+    if (c + 2 < 2 * GD && 56 - s < 32) v |= d[c + 2] << (56 - s);
+    p[k] = v;
+  }
 }
 
 // r = p mod m for p < 2^1152 (36 words).  With L = p mod 2^576 and
