@@ -179,57 +179,55 @@ RLX_HD void mul576(const uint32_t (&x)[NW], const uint32_t (&y)[NW], uint32_t (&
 
 // r = p mod m for p < 2^1152 (36 words).  With L = p mod 2^576 and
 // H = p >> 576:  p = L + H 2^240 - H (mod m), applied until the value fits
-// in 576 bits, then the final comparison with m.
+// in 576 bits, then the final comparison with m.  Each fold is an add-with-
+// carry chain (adding H 2^240, i.e. H << 16 from word 7 on) followed by a
+// subtract-with-borrow chain; every intermediate is non-negative.
 RLX_HD void mod_m(const uint32_t (&p)[2 * NW], uint32_t (&r)[NW]) {
   // T1 = L + H 2^240 - H  (>= 0, < 2^817): 26 words
   uint32_t t1[26];
   {
-    int64_t acc = 0;
+    uint32_t c = 0;
 #pragma unroll
     for (int k = 0; k < 26; ++k) {
-      int64_t v = acc;
-      if (k < NW) v += (int64_t)p[k] - (int64_t)p[NW + k];
+      const uint32_t l = k < NW ? p[k] : 0u;
+      uint32_t hs = 0;  // word k of H << 240
       if (k >= 7) {
-        // (H << 16) word k - 7: bits [32 (k-7) - 16, 32 (k-7) + 16) of H
-        const int j = k - 7;
-        uint32_t lo = (j >= 1 && j - 1 < NW) ? p[NW + j - 1] : 0u;
-        uint32_t hi = (j < NW) ? p[NW + j] : 0u;
-        v += (int64_t)(uint64_t)((lo >> 16) | (hi << 16));
+        const uint32_t hi = (k - 7 < NW) ? p[NW + k - 7] : 0u;
+        const uint32_t lo = (k >= 8 && k - 8 < NW) ? p[NW + k - 8] : 0u;
+        hs = (hi << 16) | (lo >> 16);
       }
-      t1[k] = (uint32_t)v;
-      acc = v >> 32;
+      t1[k] = k < 7 ? l : addc(l, hs, c);
     }
-  }
-  // T2 = T1 mod 2^576 + T1hi 2^240 - T1hi, T1hi = words 18..25 (< 2^241)
-  uint32_t t2[NW + 1];
-  {
-    int64_t acc = 0;
+    uint32_t br = 0;
 #pragma unroll
-    for (int k = 0; k < NW + 1; ++k) {
-      int64_t v = acc;
-      if (k < NW) v += (int64_t)t1[k];
-      if (k < 8) v -= (int64_t)t1[NW + k];
-      if (k >= 7 && k <= 16) {
-        const int j = k - 7;  // word j of (T1hi << 16), T1hi has 8 words
-        uint32_t lo = (j >= 1 && j - 1 < 8) ? t1[NW + j - 1] : 0u;
-        uint32_t hi = (j < 8) ? t1[NW + j] : 0u;
-        v += (int64_t)(uint64_t)((lo >> 16) | (hi << 16));
-      }
-      t2[k] = (uint32_t)v;
-      acc = v >> 32;
+    for (int k = 0; k < 26; ++k) t1[k] = subb(t1[k], k < NW ? p[NW + k] : 0u, br);
+  }
+  // T2 = T1 mod 2^576 + T1hi 2^240 - T1hi, T1hi = words 18..25 (< 2^241):
+  // below 2^577, with the bit above 2^576 in t
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    uint32_t hs = 0;  // word k of T1hi << 240
+    if (k >= 7) {
+      const uint32_t hi = (k - 7 < 8) ? t1[NW + k - 7] : 0u;
+      const uint32_t lo = (k >= 8 && k - 8 < 8) ? t1[NW + k - 8] : 0u;
+      hs = (hi << 16) | (lo >> 16);
     }
+    r[k] = k < 7 ? t1[k] : addc(t1[k], hs, c);
   }
-  // T3 = T2 mod 2^576 + t (2^240 - 1), t = T2 >> 576 in {0, 1}; then < m
+  uint32_t br = 0;
 #pragma unroll
-  for (int k = 0; k < NW; ++k) r[k] = t2[k];
-  const uint32_t t = t2[NW];
+  for (int k = 0; k < NW; ++k) r[k] = subb(r[k], k < 8 ? t1[NW + k] : 0u, br);
+  const uint32_t t = c - br;  // T2 >= 0, so the borrow never exceeds the carry
+  // T3 = T2 mod 2^576 + t (2^240 - 1); when t = 1, T2 mod 2^576 < 2^482, so
+  // no further overflow; then < m
   {
-    uint32_t c = t << 16;
+    uint32_t cy = t << 16;
 #pragma unroll
-    for (int k = 7; k < NW; ++k) r[k] = addc(r[k], 0u, c);
-    uint32_t br = t;
+    for (int k = 7; k < NW; ++k) r[k] = addc(r[k], 0u, cy);
+    uint32_t b2 = t;
 #pragma unroll
-    for (int k = 0; k < NW; ++k) r[k] = subb(r[k], 0u, br);
+    for (int k = 0; k < NW; ++k) r[k] = subb(r[k], 0u, b2);
   }
   canonicalize(r);
 }
