@@ -202,10 +202,14 @@ def serve_leg(rlx, torch, np, dev, plain_rate, args):
     import workloads
     from paper_2106_02504_amd.serve import Server
     mean_n = workloads.mean_serve_size()
-    srv = Server(pool=workloads.SERVE["pool"], p=P, arena_values=1 << 31, slots=3, lanes=16, seg_blocks=2048,
-                 device=dev)
+    srv = Server(pool=workloads.SERVE["pool"], p=P, arena_values=1 << 31, slots=3, lanes=args.serve_lanes,
+                 seg_blocks=args.serve_seg, device=dev)
     res = {"pool": workloads.SERVE["pool"], "p": P, "arena_values": 1 << 31, "slots": 3,
+           "lanes_per_segment": args.serve_lanes, "seg_blocks": args.serve_seg,
            "mean_request": mean_n, "runs": []}
+    # warm-up: the first launches load the kernels' code and fill the plans
+    warm = workloads.serve_requests(64, 1.0, seed=6)
+    srv.run([0.0] * len(warm), [r.stream_id for r in warm], [r.count for r in warm])
     for frac in (0.5, 0.8, 0.95):
         lam = frac * plain_rate / mean_n
         reqs = workloads.serve_requests(args.serve_requests, lam)
@@ -268,6 +272,8 @@ def main() -> int:
     ap.add_argument("--legs", default="u64,normal,single,skip,engine,batch,serve",
                     help="extra legs to time (comma list or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-lanes", type=int, default=64, help="lanes per segment of the server's plans")
+    ap.add_argument("--serve-seg", type=int, default=8192, help="steps per segment of the server's plans")
     ap.add_argument("--engine-draws", type=int, default=10 ** 6,
                     help="draws per thread in the device-engine leg (the paper's 10^6)")
     ap.add_argument("--lanes", type=int, default=0, help="force lanes per stream (0 = library's pick)")

@@ -20,7 +20,7 @@ import torch
 
 from . import Plan
 
-DEFAULT_LANES = (8, 16, 32)
+DEFAULT_LANES = (8, 16, 32, 64)
 DEFAULT_SEG_BLOCKS = (512, 1024, 2048, 4096, 8192)
 
 

@@ -98,7 +98,10 @@ class Server:
     """Request loop over `pool` streams (seed ids 0..pool-1) at luxury p."""
 
     def __init__(self, pool: int = 1_000_000, p: int = 2048, arena_values: int = 1 << 31,
-                 slots: int = 3, lanes: int = 16, seg_blocks: int = 2048, device="cuda"):
+                 slots: int = 3, lanes: int = 64, seg_blocks: int = 8192, device="cuda"):
+        # lanes / seg_blocks: 64 lanes per segment of 8192 steps measured the
+        # highest capacity on requests of 10^3..10^8 values (whole-wave
+        # segments write the longest contiguous runs)
         self.device = torch.device(device)
         self.p = p
         self.pool = pool
