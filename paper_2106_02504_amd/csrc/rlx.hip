@@ -132,13 +132,7 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
     k = v / FIELDS + r / FIELDS;
     pos = r % FIELDS;
   }
-  for (int nib = 0; nib < 16 && (k >> (4 * nib)) != 0; ++nib) {
-    const uint32_t v = (uint32_t)(k >> (4 * nib)) & 15u;
-    if (v == 0) continue;
-    uint32_t y[NW];
-    load_words(T + ((size_t)nib * TAB_COLS + v) * NW, y);
-    mulmod_inplace(x, y);
-  }
+  skip_windows(x, k, T);
   store_record(st, i, x, pos, sp);
 }
 
@@ -165,7 +159,8 @@ template <Out K, bool TRACE, int LGS>
 __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, uint32_t n,
                                                     uint64_t count, uint64_t* __restrict__ out,
                                                     uint64_t* __restrict__ trace, uint64_t trace_steps,
-                                                    const uint32_t* __restrict__ ctabs, uint32_t lg,
+                                                    const uint32_t* __restrict__ ctabs,
+                                                    const uint32_t* __restrict__ T, uint32_t lg,
                                                     uint32_t p, uint32_t* __restrict__ err,
                                                     int force_general) {
   // Per-lane state kept across the loop is x plus four 32-bit words (record
@@ -200,7 +195,7 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
 
   // lane l starts at block l: X_l = A^l X_0 (bits 6 and up of l are the
   // same for the whole wave)
-  if (STAGED) advance(x, l, ctabs, force);
+  if (STAGED) skip_windows(x, l, T);
   const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * FOLD_ROW_WORDS;
 
   for (uint32_t k = 0;; ++k) {
@@ -498,7 +493,7 @@ int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint
   const uint32_t lgs = lg < 6 ? lg : 6;
 #define RLX_GEN(L)                                                                                    \
   case L:                                                                                             \
-    k_generate<K, TRACE, L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, trace, trace_steps, t.C, lg, p, \
+    k_generate<K, TRACE, L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, trace, trace_steps, t.C, t.T, lg, p, \
                                                      err, force_general);                             \
     break;
   switch (lgs) {

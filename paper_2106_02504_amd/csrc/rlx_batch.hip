@@ -64,6 +64,7 @@ struct Header {
   uint32_t n_items;
   uint32_t pad[2];
   const uint32_t* C[MAX_LEVELS];  // folded multipliers A^(2^g) of each level
+  const uint32_t* T[MAX_LEVELS];  // window tables A^(j 16^i) of each level
   uint32_t p[MAX_LEVELS];
 };
 
@@ -91,6 +92,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ s
     const Item item = items[it];
     const uint32_t slot = __builtin_amdgcn_readfirstlane(item.slot);
     const uint32_t* __restrict__ ctabs = hdr->C[slot];
+    const uint32_t* __restrict__ wtabs = hdr->T[slot];
     const uint32_t p = __builtin_amdgcn_readfirstlane(hdr->p[slot]);
     bool active = team < item.nseg;
     uint32_t si = item.seg0 + team;
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ s
       }
     }
     if (!active) set_one(x);
-    advance(x, first, ctabs, false);
+    skip_windows(x, first, wtabs);
     const uint32_t* __restrict__ ctab = ctabs + (size_t)LGS * FOLD_ROW_WORDS;
     // Output window of the segment: base[u] for u < span, with the
     // segment's first field at u = rel (rel >= -11; span < 2^30 because
@@ -274,6 +276,7 @@ int upload(rlx_plan* plan, const Planned& pl, hipStream_t s) {
     const int rc = tables(pl.ps[k], s, &t);
     if (rc) return rc;
     hd.C[k] = t.C;
+    hd.T[k] = t.T;
     hd.p[k] = pl.ps[k];
   }
   // the previous upload must have left the staging buffers

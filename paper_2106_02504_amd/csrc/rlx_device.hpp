@@ -96,15 +96,22 @@ __device__ __forceinline__ void mulmod_inplace(uint32_t (&x)[NW], const uint32_t
   copy_words(x, r);
 }
 
-// x <- A^e x for a per-lane exponent e < 2^64: one folded step by A^(2^g)
-// for every set bit g of e.  The steps run in increasing g; a bit that no
-// lane of the wave has set is skipped by the whole wave.
-__device__ __forceinline__ void advance(uint32_t (&x)[NW], uint64_t e, const uint32_t* __restrict__ ctabs,
-                                        bool force) {
+// X <- A^e X by 4-bit windows: one generic multiplication per non-zero
+// hexadecimal digit of e by the table entry A^(v 16^i) (rows 0..15 of T,
+// section 2.4).  The wave runs as many rounds as its longest exponent has
+// digits.  Starting the lanes of a record this way (e = lane index, or the
+// segment's first step plus the lane index) costs one per-lane
+// multiplication for e < 16, half the work of the four masked folded steps
+// that the bits of e would take.
+__device__ __forceinline__ void skip_windows(uint32_t (&x)[NW], uint64_t e, const uint32_t* __restrict__ T) {
 #pragma unroll 1
-  for (uint32_t g = 0; g < 64 && __any((e >> g) != 0); ++g) {
-    const bool set = ((e >> g) & 1u) != 0;
-    if (__any(set) && set) step(x, constant_table(ctabs + (size_t)g * FOLD_ROW_WORDS), force, SgprBarrier());
+  for (int nib = 0; nib < 16 && __any((e >> (4 * nib)) != 0); ++nib) {
+    const uint32_t v = (uint32_t)(e >> (4 * nib)) & 15u;
+    if (v != 0) {
+      uint32_t y[NW];
+      load_words(T + ((size_t)nib * TAB_COLS + v) * NW, y);
+      mulmod_inplace(x, y);
+    }
   }
 }
 
