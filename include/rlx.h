@@ -330,7 +330,9 @@ int rlx_test_to_ranlux(const uint64_t *x, uint64_t *d, uint32_t *carry,
  *   mode 3  as 0 with rlx_engine_next_normal;
  *   mode 4  as 0 with rlx_engine_next_u48 (bits in out);
  *   mode 5  out[i] = the sum, in draw order, of `count` doubles (the
- *           paper's GPU benchmark, section 4.2); store the record. */
+ *           paper's GPU benchmark, section 4.2); store the record;
+ *   mode 6  as 0, but thread i draws in bursts of (i mod 3) + 1 values
+ *           inside per-thread branches (divergent calls). */
 int rlx_test_engine(rlx_state *states, uint64_t n, uint64_t count,
                     double *out, uint32_t mode, uint32_t p, void *stream);
 

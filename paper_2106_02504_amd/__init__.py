@@ -257,7 +257,7 @@ def get_tables(p: int, device=None) -> EngineTables:
     return t
 
 
-ENGINE_MODES = {"f64": 0, "seed": 1, "skip": 2, "normal": 3, "u48": 4, "sum": 5}
+ENGINE_MODES = {"f64": 0, "seed": 1, "skip": 2, "normal": 3, "u48": 4, "sum": 5, "divergent": 6}
 
 
 def test_engine(states: torch.Tensor, count: int, p: int, mode: str) -> torch.Tensor:

@@ -31,6 +31,21 @@ __global__ __launch_bounds__(ENGINE_BLOCK) void k_engine(rlx_state* __restrict__
     double sum = 0.0;
     for (uint64_t j = 0; j < count; ++j) sum += rlx_engine_next_f64(e, t);
     out[i] = sum;
+  } else if constexpr (mode == 6) {
+    // divergent calls: in each round, thread i draws (i mod 3) + 1 values
+    // inside a branch of its own, so lanes of a wave call the engine at
+    // different times and positions
+    double* row = out + i * count;
+    const uint32_t burst = (uint32_t)(i % 3) + 1;
+    uint64_t j = 0;
+    while (j < count) {
+      if ((i & 1) == 0) {
+        for (uint32_t b = 0; b < burst && j < count; ++b) row[j++] = rlx_engine_next_f64(e, t);
+      } else {
+        for (uint32_t b = 0; b < burst && j < count; ++b) row[j++] = rlx_engine_next_f64(e, t);
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
   } else {
     double* row = out + i * count;
     for (uint64_t j = 0; j < count; ++j) {
@@ -54,7 +69,7 @@ __global__ __launch_bounds__(ENGINE_BLOCK) void k_engine(rlx_state* __restrict__
 extern "C" int rlx_test_engine(rlx_state* states, uint64_t n, uint64_t count, double* out, uint32_t mode,
                                uint32_t p, void* stream) {
   if (n == 0) return RLX_OK;
-  if (!states || !out || mode > 5) return RLX_EINVAL;
+  if (!states || !out || mode > 6) return RLX_EINVAL;
   if ((reinterpret_cast<uintptr_t>(states) & 15) != 0 || (reinterpret_cast<uintptr_t>(out) & 7) != 0)
     return RLX_EINVAL;
   if (n > RLX_MAX_STREAMS || (mode != 5 && count > UINT64_MAX / 8 / n)) return RLX_EINVAL;
@@ -68,7 +83,7 @@ extern "C" int rlx_test_engine(rlx_state* states, uint64_t n, uint64_t count, do
 #define RLX_ENGINE_MODE(M) \
   case M: k_engine<M><<<(unsigned)blocks, ENGINE_BLOCK, 0, s>>>(states, n, count, out, t); break;
     RLX_ENGINE_MODE(0) RLX_ENGINE_MODE(1) RLX_ENGINE_MODE(2) RLX_ENGINE_MODE(3) RLX_ENGINE_MODE(4)
-    RLX_ENGINE_MODE(5)
+    RLX_ENGINE_MODE(5) RLX_ENGINE_MODE(6)
 #undef RLX_ENGINE_MODE
   }
   return hipGetLastError() == hipSuccess ? RLX_OK : RLX_EHIP;

@@ -104,6 +104,22 @@ def test_engine_normals_equal_bulk_normals():
     assert np.all(err <= 2.0 ** -49 * np.abs(want) + 2.0 ** -70)
 
 
+def test_engine_divergent_calls():
+    # lanes draw in bursts of 1..3 values under per-lane branches: the lazy
+    # wave-synchronised advance must still give every lane its own sequence
+    p = 2048
+    recs = staggered_records(200, p, 11)
+    a = records_to_tensor(recs)
+    b = a.clone()
+    got = rlx.test_engine(a, 77, p, "divergent")
+    bulk = rlx.generate_f64(b, 77, p)
+    torch.cuda.synchronize()
+    assert torch.equal(got, bulk) and torch.equal(a, b)
+    for i in (0, 1, 2, 65, 199):
+        want, _, _ = O.draws_f64(recs[i][0], recs[i][1], p, 77)
+        assert got[i].cpu().tolist() == want
+
+
 def test_engine_sum_in_draw_order():
     # the paper's GPU benchmark form: each thread sums its draws in order
     p = 2048
