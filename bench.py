@@ -9,6 +9,10 @@ doubles/s over whole steps.
 
 Other legs (reported beside the headline in the same JSON line):
   u64        the same step writing the 48-bit integers instead of doubles
+  f32        the same streams writing float32, one RANLUX number each
+             (8192 per stream: the same 2 GiB), checked against the doubles
+  lcg52      the legacy conversion (52 raw LCG bits per double, 11 per
+             step; biased, for comparison only), 4096 per stream
   single     one stream (id 1), 2^20 doubles plus the state after each step
   skip       2^20 seeded states, each skipped by a log-uniform offset in
              [1, 2^64) generator steps
@@ -269,7 +273,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=8192)
-    ap.add_argument("--legs", default="u64,normal,single,skip,engine,batch,serve",
+    ap.add_argument("--legs", default="u64,normal,f32,lcg52,single,skip,engine,batch,serve",
                     help="extra legs to time (comma list or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-lanes", type=int, default=64, help="lanes per segment of the server's plans")
@@ -408,6 +412,33 @@ def main() -> int:
                           "mean": float(flat.mean()), "var": float(flat.var()),
                           "workload": "many-streams shape, Box-Muller on field pairs"}
         del outn, flat
+    if "f32" in wanted:
+        outf = torch.empty((N_STREAMS, 2 * DRAWS), dtype=torch.float32, device=dev)
+
+        def step_f():
+            rlx.init_streams(st, P, id0=0)
+            rlx.generate_f32(st, 2 * DRAWS, P, out=outf)
+        dt = timed(step_f, stream, max(5, args.steps // 2), 2, torch)
+        # the pair of floats at position j reassembles the 48-bit value j
+        lo = (outf[:, 0::2].to(torch.float64) * 2.0 ** 24).to(torch.int64)
+        hi = (outf[:, 1::2].to(torch.float64) * 2.0 ** 24).to(torch.int64)
+        same = bool(torch.equal(lo + (hi << 24), (out * 2.0 ** 48).to(torch.int64)))
+        del lo, hi
+        legs["f32"] = {"value": 2 * total / dt, "unit": "floats/s", "ms_per_step": dt * 1e3,
+                       "gb_per_s": 2 * total * 4 / dt / 1e9, "pairs_equal_f64_bits": same,
+                       "workload": f"many-streams shape, {2 * DRAWS} float32 per stream (24 per step)"}
+        del outf
+    if "lcg52" in wanted:
+        out52 = torch.empty((N_STREAMS, DRAWS), dtype=torch.float64, device=dev)
+
+        def step_52():
+            rlx.init_streams(st, P, id0=0)
+            rlx.generate_f64_lcg52(st, DRAWS, P, out=out52)
+        dt = timed(step_52, stream, max(5, args.steps // 2), 2, torch)
+        legs["lcg52"] = {"value": total / dt, "unit": "doubles/s", "ms_per_step": dt * 1e3,
+                         "multiples_of_2^-52": bool(((out52 * 2.0 ** 52).frac() == 0).all()),
+                         "workload": "many-streams shape, legacy raw-LCG doubles (11 per step)"}
+        del out52
     if "engine" in wanted:
         legs["engine"] = engine_leg(rlx, torch, dev, args)
 

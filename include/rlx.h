@@ -170,6 +170,30 @@ int rlx_generate_u64(rlx_state *states, uint64_t n, uint64_t count,
 int rlx_generate_normal_f64(rlx_state *states, uint64_t n, uint64_t count,
                             double *out, uint32_t p, void *stream);
 
+/* Float32 draws, one RANLUX number each: v 2^-24 in [0, 1), exact in
+ * binary32 (section 2.3 converts back to the 24-bit RANLUX numbers because
+ * they are equally distributed).  A step gives 24 floats, its numbers in
+ * the order the subtract-with-borrow recurrence produced them.  A record's
+ * position counts 48-bit fields, which hold two numbers each, so `count`
+ * (floats per record, row i at out + i * count) must be even and advances
+ * the record by count / 2 positions: floats 2j and 2j + 1 of a row are the
+ * low and high 24 bits of the value j that rlx_generate_u64 gives.  Odd
+ * count (also with n = 0) or count / 2 > RLX_MAX_COUNT -> RLX_EINVAL.  out
+ * must be 8-byte aligned. */
+int rlx_generate_f32(rlx_state *states, uint64_t n, uint64_t count,
+                     float *out, uint32_t p, void *stream);
+
+/* Legacy doubles, for comparison only: the earlier conversion that section
+ * 2.3 describes and rejects as biased (the top bits of X < m are 0 slightly
+ * more often), 52 bits of the LCG state itself as the mantissa.  Value k of
+ * a step is bits [52k, 52k + 52) of X, k = 0..10, as v 2^-52 (the top 4
+ * bits of X are unused); 11 values per step, and the record's pos counts
+ * these values: records with pos = 11 (or > 11) are flagged RLX_ERR_BAD_POS
+ * and left unwritten.  A record moves between this call and the 48-bit
+ * ones at pos = 0 only.  Layout and limits as rlx_generate_f64. */
+int rlx_generate_f64_lcg52(rlx_state *states, uint64_t n, uint64_t count,
+                           double *out, uint32_t p, void *stream);
+
 /* rlx_generate_f64 that also writes the LCG state of every step it visits:
  * trace[(i * steps_per_stream + t) * 9 + w], t = 0 is the state on entry and
  * t = 1..A the states after each of the A = (pos + count) / 12 advances, so
@@ -275,6 +299,11 @@ int rlx_plan_info(const rlx_plan *plan, uint64_t *segments, uint64_t *items,
  * request's range. */
 int rlx_plan_generate_f64(rlx_plan *plan, const rlx_state *states, double *out, void *stream);
 int rlx_plan_generate_u64(rlx_plan *plan, const rlx_state *states, uint64_t *out, void *stream);
+/* Float32 form of a plan (as rlx_generate_f32): each request's positions
+ * give two floats each, so request value j goes to
+ * out[2 (out_offset + j)] and out[2 (out_offset + j) + 1]; out must hold
+ * 2 (out_offset + count) floats for every request. */
+int rlx_plan_generate_f32(rlx_plan *plan, const rlx_state *states, float *out, void *stream);
 
 /* Free the plan (synchronises the device first). */
 int rlx_plan_destroy(rlx_plan *plan);
@@ -332,7 +361,10 @@ int rlx_test_to_ranlux(const uint64_t *x, uint64_t *d, uint32_t *carry,
  *   mode 5  out[i] = the sum, in draw order, of `count` doubles (the
  *           paper's GPU benchmark, section 4.2); store the record;
  *   mode 6  as 0, but thread i draws in bursts of (i mod 3) + 1 values
- *           inside per-thread branches (divergent calls). */
+ *           inside per-thread branches (divergent calls);
+ *   mode 7  as 0 with rlx_engine_next_f32x2: slot j of the row holds the
+ *           two floats of position j (the row as floats is what
+ *           rlx_generate_f32 writes for 2 count floats). */
 int rlx_test_engine(rlx_state *states, uint64_t n, uint64_t count,
                     double *out, uint32_t mode, uint32_t p, void *stream);
 

@@ -9,6 +9,7 @@
  *     rlx_engine e;
  *     rlx_engine_load(e, st + i);                 // or rlx_engine_seed(e, id, t)
  *     double u = rlx_engine_next_f64(e, t);       // ... as often as needed
+ *     float2 f = rlx_engine_next_f32x2(e, t);     // or two 24-bit floats
  *     rlx_engine_store(e, st + i, t.p);
  *   }
  *
@@ -186,6 +187,13 @@ __device__ __forceinline__ uint64_t rlx_engine_next_u48(rlx_engine& e, const rlx
 /* Next uniform double v 2^-48 in [0, 1) (exact). */
 __device__ __forceinline__ double rlx_engine_next_f64(rlx_engine& e, const rlx_engine_tables& t) {
     return (double)rlx_engine_next_u48(e, t) * 0x1p-48;
+}
+
+/* Next position as two float32 values, its RANLUX numbers v 2^-24 (exact),
+ * the older number in .x: the floats rlx_generate_f32 writes there. */
+__device__ __forceinline__ float2 rlx_engine_next_f32x2(rlx_engine& e, const rlx_engine_tables& t) {
+    const uint64_t v = rlx_engine_next_u48(e, t);
+    return make_float2((float)(uint32_t)(v & 0xFFFFFFu) * 0x1p-24f, (float)(uint32_t)(v >> 24) * 0x1p-24f);
 }
 
 /* Next standard normal: Box-Muller on the field pair of the position, as

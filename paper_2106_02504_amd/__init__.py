@@ -52,6 +52,8 @@ _SIGS = {
     "rlx_generate_f64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_u64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_normal_f64": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
+    "rlx_generate_f32": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
+    "rlx_generate_f64_lcg52": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_get_tables": (_int, [_u32, _vp, _vp]),
     "rlx_test_engine": (_int, [_vp, _u64, _u64, _vp, _u32, _u32, _vp]),
     "rlx_generate_f64_trace": (_int, [_vp, _u64, _u64, _vp, _vp, _u64, _u32, _vp]),
@@ -64,6 +66,7 @@ _SIGS = {
     "rlx_plan_info": (_int, [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u64), ctypes.POINTER(_u64)]),
     "rlx_plan_generate_f64": (_int, [_vp, _vp, _vp, _vp]),
     "rlx_plan_generate_u64": (_int, [_vp, _vp, _vp, _vp]),
+    "rlx_plan_generate_f32": (_int, [_vp, _vp, _vp, _vp]),
     "rlx_plan_destroy": (_int, [_vp]),
     "rlx_plan_dry_run": (_int, [_vp, _u64, _u32, _u64, ctypes.POINTER(_u64), ctypes.POINTER(_u64),
                                 ctypes.POINTER(_u64), _vp, _u64]),
@@ -242,6 +245,29 @@ def generate_normal_f64(states: torch.Tensor, count: int, p: int, out: torch.Ten
     return out
 
 
+def generate_f32(states: torch.Tensor, count: int, p: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """`count` (even) float32 values per record, shape [n, count]: one RANLUX
+    number v 2^-24 each, 24 per generator step (section 2.3); advances each
+    record by count / 2 positions."""
+    n = _need_states(states)
+    out = _out(states, count, torch.float32, out)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_generate_f32(states.data_ptr(), n, count, out.data_ptr(), p, _stream()), "rlx_generate_f32")
+    return out
+
+
+def generate_f64_lcg52(states: torch.Tensor, count: int, p: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Legacy doubles from 52-bit slices of the LCG state (biased; for
+    comparison only, section 2.3), shape [n, count], 11 per step; record
+    positions count these values."""
+    n = _need_states(states)
+    out = _out(states, count, torch.float64, out)
+    with torch.cuda.device(states.device):
+        _check(lib().rlx_generate_f64_lcg52(states.data_ptr(), n, count, out.data_ptr(), p, _stream()),
+               "rlx_generate_f64_lcg52")
+    return out
+
+
 class EngineTables(ctypes.Structure):
     """rlx_engine_tables: device addresses of a luxury level's tables, to be
     passed by value to kernels that use the device-side engine."""
@@ -257,13 +283,14 @@ def get_tables(p: int, device=None) -> EngineTables:
     return t
 
 
-ENGINE_MODES = {"f64": 0, "seed": 1, "skip": 2, "normal": 3, "u48": 4, "sum": 5, "divergent": 6}
+ENGINE_MODES = {"f64": 0, "seed": 1, "skip": 2, "normal": 3, "u48": 4, "sum": 5, "divergent": 6, "f32": 7}
 
 
 def test_engine(states: torch.Tensor, count: int, p: int, mode: str) -> torch.Tensor:
     """Test hook: run the device-side engine (rlx_engine.h) from a kernel
     written as user code, one thread per record; returns [n, count] values
-    (float64, or the u48 bits as int64 for mode "u48"; [n] sums for "sum")."""
+    (float64, or the u48 bits as int64 for mode "u48"; [n] sums for "sum";
+    [n, 2 count] float32 for "f32")."""
     n = _need_states(states)
     m = ENGINE_MODES[mode]
     shape = (n,) if mode == "sum" else (n, count)
@@ -271,7 +298,11 @@ def test_engine(states: torch.Tensor, count: int, p: int, mode: str) -> torch.Te
     with torch.cuda.device(states.device):
         _check(lib().rlx_test_engine(states.data_ptr(), n, count, out.data_ptr(), m, p, _stream()),
                "rlx_test_engine")
-    return out.view(torch.int64) if mode == "u48" else out
+    if mode == "u48":
+        return out.view(torch.int64)
+    if mode == "f32":
+        return out.view(torch.float32)
+    return out
 
 
 def generate_f64_trace(states: torch.Tensor, count: int, p: int):
@@ -334,11 +365,27 @@ class Plan:
             _check(lib().rlx_plan_create(ctypes.byref(self._h), req.ctypes.data, req.shape[0], lanes, seg_blocks,
                                          capacity_segments, _stream()), "rlx_plan_create")
         self.lanes, self.seg_blocks = lanes, seg_blocks
+        self.extent = self._extent(req)
+
+    @staticmethod
+    def _extent(req) -> int:
+        """Output elements the requests need: max of out_offset + count (the
+        library accepted them, so these sums do not overflow)."""
+        live = req[req["count"] > 0]
+        return int((live["out_offset"] + live["count"]).max()) if live.shape[0] else 0
 
     def update(self, requests) -> None:
         req = _np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
         with torch.cuda.device(self.device):
             _check(lib().rlx_plan_update(self._h, req.ctypes.data, req.shape[0], _stream()), "rlx_plan_update")
+        self.extent = self._extent(req)
+
+    def _check_out(self, states: torch.Tensor, out: torch.Tensor, dtype: torch.dtype, per_value: int) -> None:
+        _need_states(states)
+        if out.dtype != dtype or not out.is_contiguous() or out.device != states.device:
+            raise ValueError(f"out must be a contiguous {dtype} tensor on the states' device")
+        if out.numel() < per_value * self.extent:
+            raise ValueError(f"out holds {out.numel()} elements; the requests need {per_value * self.extent}")
 
     def info(self) -> dict:
         a, b, c = _u64(0), _u64(0), _u64(0)
@@ -346,21 +393,26 @@ class Plan:
         return {"segments": a.value, "items": b.value, "values": c.value}
 
     def generate_f64(self, states: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
-        _need_states(states)
-        if out.dtype != torch.float64 or not out.is_contiguous() or out.device != states.device:
-            raise ValueError("out must be a contiguous float64 tensor on the states' device")
+        self._check_out(states, out, torch.float64, 1)
         with torch.cuda.device(states.device):
             _check(lib().rlx_plan_generate_f64(self._h, states.data_ptr(), out.data_ptr(), _stream()),
                    "rlx_plan_generate_f64")
         return out
 
     def generate_u64(self, states: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
-        _need_states(states)
-        if out.dtype != torch.int64 or not out.is_contiguous() or out.device != states.device:
-            raise ValueError("out must be a contiguous int64 tensor on the states' device")
+        self._check_out(states, out, torch.int64, 1)
         with torch.cuda.device(states.device):
             _check(lib().rlx_plan_generate_u64(self._h, states.data_ptr(), out.data_ptr(), _stream()),
                    "rlx_plan_generate_u64")
+        return out
+
+    def generate_f32(self, states: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """Two floats per requested position: value j of a request goes to
+        out[2 (out_offset + j)] and out[2 (out_offset + j) + 1]."""
+        self._check_out(states, out, torch.float32, 2)
+        with torch.cuda.device(states.device):
+            _check(lib().rlx_plan_generate_f32(self._h, states.data_ptr(), out.data_ptr(), _stream()),
+                   "rlx_plan_generate_f32")
         return out
 
     def close(self) -> None:

@@ -4,7 +4,8 @@
 //   k_tab_base / k_tab_fill / k_tab_fold   per-luxury-level constant tables
 //   k_init                                 seeding        (section 2.4)
 //   k_skip                                 skip-ahead     (section 2.4)
-//   k_generate<U64|F64|NORMAL, trace, LGS> draw values (sections 2.1-2.3)
+//   k_generate<U64|F64|NORMAL|F32, trace, LGS> draw values (sections 2.1-2.3)
+//   k_generate_lcg52<LGS>                  legacy raw-LCG doubles (section 2.3)
 //   k_test_*                               generic arithmetic for tests
 // The batched persistent kernel and its planner are in rlx_batch.hip.
 #include <hip/hip_runtime.h>
@@ -228,6 +229,87 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
       group_store<LGS>(stage, tid_blk, ls, jb, count, active, row);
     }
     if (__any(live && t + (1u << lg) <= nadv)) step(x, constant_table(ctab), force, SgprBarrier());
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Legacy doubles from raw LCG bits, for comparison only (section 2.3 names
+// this earlier conversion and drops it as biased): value k of step t is bits
+// [52k, 52k + 52) of X_t, k < 11, as v 2^-52, and the record's pos counts
+// these values (0..10).  Same lane interleaving as k_generate (lane l takes
+// steps l, l + G, ...); no RANLUX conversion.  A lane's 11 values go through
+// an LDS slot so that each store instruction writes gs consecutive doubles
+// of the row.
+
+constexpr int LCG52_VALUES = 11;
+
+// Bits [52k, 52k + 52) of X as the double v 2^-52: 0x3FF << 52 | v is
+// 1 + v 2^-52, and subtracting 1 is exact.  k is a constant after unrolling;
+// bits past 575 never reach the 52 kept (k = 10 ends at bit 571).
+__device__ __forceinline__ double lcg52_value(const uint32_t (&x)[NW], int k) {
+  const int b = 52 * k, w = b >> 5, s = b & 31;
+  const uint32_t w2 = x[w + 2 < NW ? w + 2 : NW - 1];
+  const uint32_t lo = s ? __builtin_amdgcn_alignbit(x[w + 1], x[w], s) : x[w];
+  const uint32_t hi = s ? __builtin_amdgcn_alignbit(w2, x[w + 1], s) : x[w + 1];
+  return bits_to_f64(lo, (hi & 0xFFFFFu) | 0x3FF00000u) - 1.0;
+}
+
+template <int LGS>
+__global__ __launch_bounds__(BLOCK) void k_generate_lcg52(rlx_state* __restrict__ st, uint32_t n, uint64_t count,
+                                                          double* __restrict__ out,
+                                                          const uint32_t* __restrict__ ctabs,
+                                                          const uint32_t* __restrict__ T, uint32_t lg, uint32_t p,
+                                                          uint32_t* __restrict__ err) {
+  constexpr uint32_t gs = 1u << LGS;  // lanes of a record inside one wave
+  __shared__ double stage[BLOCK * LCG52_VALUES];
+  const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t i = (uint32_t)(tid >> lg);
+  const uint32_t l = (uint32_t)tid & ((1u << lg) - 1u);
+
+  uint32_t x[NW];
+  uint32_t pos = 0, sp = 0;
+  bool active = (tid >> lg) < n;
+  if (active) {
+    load_record(st, i, x, pos, sp);
+    uint32_t bad = check_record(x, pos, sp, p);
+    if (pos == LCG52_VALUES) bad |= RLX_ERR_BAD_POS;
+    if (bad) {
+      if (l == 0) atomicOr(err, bad);
+      active = false;
+    }
+  }
+  if (!active) {
+    set_one(x);
+    pos = 0;
+  }
+  const uint32_t nadv = (uint32_t)((pos + count) / LCG52_VALUES);
+  skip_windows(x, l, T);
+  const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * FOLD_ROW_WORDS;
+  const uint32_t ls = l & (gs - 1);
+  double* const slot = stage + (size_t)threadIdx.x * LCG52_VALUES;
+  const double* const grp = stage + (size_t)(threadIdx.x - ls) * LCG52_VALUES;
+  double* const row = out + (uint64_t)i * count;
+
+  for (uint32_t k = 0;; ++k) {
+    const uint32_t t = l + (k << lg);
+    const bool live = active && t <= nadv;
+    if (!__any(live)) break;
+    if (live && t == nadv) store_record(st, i, x, (uint32_t)((pos + count) % LCG52_VALUES), p);
+#pragma unroll
+    for (int f = 0; f < LCG52_VALUES; ++f) slot[f] = lcg52_value(x, f);
+    wave_sync();
+    // the group's blocks t - ls .. t - ls + gs - 1 hold values from u0 on;
+    // value q gs + ls of the group goes to row[u0 + q gs + ls] if in range
+    if (active) {
+      uint64_t u = (uint64_t)((int64_t)((uint64_t)(t - ls) * LCG52_VALUES) - (int64_t)pos + (int64_t)ls);
+#pragma unroll
+      for (int q = 0; q < LCG52_VALUES; ++q) {
+        if (u < count) row[u] = grp[q * gs + ls];
+        u += gs;
+      }
+    }
+    wave_sync();
+    if (__any(live && t + (1u << lg) <= nadv)) step(x, constant_table(ctab), false, SgprBarrier());
   }
 }
 
@@ -463,28 +545,37 @@ uint32_t lanes_for(uint64_t n, uint64_t count) {
   return o ? o : auto_lanes(n, count);
 }
 
-template <Out K, bool TRACE>
-int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint64_t* trace,
-                  uint64_t trace_steps, uint32_t p, void* stream, int force_general) {
-  if (n == 0 || count == 0) return RLX_OK;
+// Argument checks shared by the generate calls; on success *lg is log2 of
+// the lanes per record and *grid covers n << lg lanes.
+int generate_args(const rlx_state* states, uint64_t n, uint64_t count, const void* out, uint32_t p,
+                  uint32_t* lg, dim3* grid) {
   if (!states || !out || !valid_p(p)) return RLX_EINVAL;
   if (!aligned(states, 16) || !aligned(out, 8)) return RLX_EINVAL;
   if (n > RLX_MAX_STREAMS || count > RLX_MAX_COUNT) return RLX_EINVAL;
   if (count > UINT64_MAX / 8 / n) return RLX_EINVAL;
+  const uint32_t G = lanes_for(n, count);
+  *lg = (uint32_t)__builtin_ctz(G);
+  if (n > (UINT64_MAX >> *lg)) return RLX_EINVAL;
+  return grid_for(n << *lg, grid) ? RLX_OK : RLX_EINVAL;
+}
+
+template <Out K, bool TRACE>
+int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint64_t* trace,
+                  uint64_t trace_steps, uint32_t p, void* stream, int force_general) {
+  if (n == 0 || count == 0) return RLX_OK;
+  uint32_t lg;
+  dim3 grid;
+  int rc = generate_args(states, n, count, out, p, &lg, &grid);
+  if (rc) return rc;
   if (TRACE) {
     if (!trace || !aligned(trace, 8)) return RLX_EINVAL;
     if (count > UINT64_MAX - 11) return RLX_EINVAL;
     const uint64_t need = (11 + count) / 12 + 1;
     if (trace_steps < need || trace_steps > UINT64_MAX / 72 / n) return RLX_EINVAL;
   }
-  const uint32_t G = lanes_for(n, count);
-  const uint32_t lg = (uint32_t)__builtin_ctz(G);
-  if (n > (UINT64_MAX >> lg)) return RLX_EINVAL;
-  dim3 grid;
-  if (!grid_for(n << lg, &grid)) return RLX_EINVAL;
   hipStream_t s = as_stream(stream);
   Tables t;
-  int rc = tables(p, s, &t);
+  rc = tables(p, s, &t);
   if (rc) return rc;
   uint32_t* err;
   rc = error_word(s, &err);
@@ -500,6 +591,31 @@ int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint
     RLX_GEN(0) RLX_GEN(1) RLX_GEN(2) RLX_GEN(3) RLX_GEN(4) RLX_GEN(5) RLX_GEN(6)
   }
 #undef RLX_GEN
+  return launch_status();
+}
+
+int generate_lcg52_impl(rlx_state* states, uint64_t n, uint64_t count, double* out, uint32_t p, void* stream) {
+  if (n == 0 || count == 0) return RLX_OK;
+  uint32_t lg;
+  dim3 grid;
+  int rc = generate_args(states, n, count, out, p, &lg, &grid);
+  if (rc) return rc;
+  hipStream_t s = as_stream(stream);
+  Tables t;
+  rc = tables(p, s, &t);
+  if (rc) return rc;
+  uint32_t* err;
+  rc = error_word(s, &err);
+  if (rc) return rc;
+  const uint32_t lgs = lg < 6 ? lg : 6;
+#define RLX_GEN52(L)                                                                                  \
+  case L:                                                                                             \
+    k_generate_lcg52<L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, out, t.C, t.T, lg, p, err); \
+    break;
+  switch (lgs) {
+    RLX_GEN52(0) RLX_GEN52(1) RLX_GEN52(2) RLX_GEN52(3) RLX_GEN52(4) RLX_GEN52(5) RLX_GEN52(6)
+  }
+#undef RLX_GEN52
   return launch_status();
 }
 
@@ -645,6 +761,16 @@ int rlx_generate_u64(rlx_state* states, uint64_t n, uint64_t count, uint64_t* ou
 int rlx_generate_normal_f64(rlx_state* states, uint64_t n, uint64_t count, double* out, uint32_t p,
                             void* stream) {
   return generate_impl<Out::NORMAL, false>(states, n, count, out, nullptr, 0, p, stream, 0);
+}
+
+int rlx_generate_f32(rlx_state* states, uint64_t n, uint64_t count, float* out, uint32_t p, void* stream) {
+  if (count & 1) return RLX_EINVAL;
+  return generate_impl<Out::F32, false>(states, n, count / 2, out, nullptr, 0, p, stream, 0);
+}
+
+int rlx_generate_f64_lcg52(rlx_state* states, uint64_t n, uint64_t count, double* out, uint32_t p,
+                           void* stream) {
+  return generate_lcg52_impl(states, n, count, out, p, stream);
 }
 
 int rlx_generate_f64_trace(rlx_state* states, uint64_t n, uint64_t count, double* out, uint64_t* trace,

@@ -411,6 +411,10 @@ int rlx_plan_generate_u64(rlx_plan* plan, const rlx_state* states, uint64_t* out
   return plan_launch<Out::U64>(plan, states, out, stream);
 }
 
+int rlx_plan_generate_f32(rlx_plan* plan, const rlx_state* states, float* out, void* stream) {
+  return plan_launch<Out::F32>(plan, states, out, stream);
+}
+
 int rlx_plan_dry_run(const rlx_request* reqs, uint64_t n, uint32_t lanes, uint64_t seg_blocks,
                      uint64_t* n_segments, uint64_t* n_items, uint64_t* total_values, uint64_t* segments,
                      uint64_t max_segments) {

@@ -116,8 +116,9 @@ __device__ __forceinline__ void skip_windows(uint32_t (&x)[NW], uint64_t e, cons
 }
 
 // What a generate kernel writes for each position: the 48-bit integer, the
-// double v 2^-48, or a standard normal from the position's field pair.
-enum class Out { U64, F64, NORMAL };
+// double v 2^-48, a standard normal from the position's field pair, or the
+// position's two RANLUX numbers as float32 (low number first).
+enum class Out { U64, F64, NORMAL, F32 };
 
 __device__ __forceinline__ double bits_to_f64(uint32_t lo, uint32_t hi) {
   const uint64_t b = ((uint64_t)hi << 32) | lo;
@@ -145,16 +146,34 @@ __device__ __forceinline__ void pair_f64(uint32_t w0, uint32_t w1, uint32_t w2, 
   u_odd = bits_to_f64(o_lo, o_hi) - 16.0;
 }
 
+// A RANLUX number (24 bits) as the float v 2^-24: the conversion is exact
+// for v < 2^24 and so is the power-of-two scaling.
+__device__ __forceinline__ uint32_t number_f32_bits(uint32_t v) {
+  const float f = (float)v * 0x1p-24f;
+  uint32_t b;
+  __builtin_memcpy(&b, &f, 4);
+  return b;
+}
+
 // Both output values of the field pair held in words (w0, w1, w2).  For
 // normals, Box-Muller on the pair: r = sqrt(-2 ln(1 - u1)) with u1 the even
 // field's double, and the even and odd positions get r cos(2 pi u2) and
 // r sin(2 pi u2) = r cos(2 pi u2 - pi / 2); 1 - u1 is in (0, 1] and
-// 2 u2 - 1/2 is exact.
+// 2 u2 - 1/2 is exact.  For float32 each position holds its two RANLUX
+// numbers (bits 0..23 and 24..47 of the field), the older one in the low
+// 32 bits, i.e. first in memory.
 template <Out K>
 __device__ __forceinline__ void pair_values(uint32_t w0, uint32_t w1, uint32_t w2, uint64_t& a, uint64_t& b) {
   if constexpr (K == Out::U64) {
     a = ((uint64_t)(w1 & 0xFFFFu) << 32) | w0;
     b = ((uint64_t)(w2 >> 16) << 32) | __builtin_amdgcn_alignbit(w2, w1, 16);
+  } else if constexpr (K == Out::F32) {
+    const uint32_t n0 = w0 & 0xFFFFFFu;
+    const uint32_t n1 = __builtin_amdgcn_alignbit(w1, w0, 24) & 0xFFFFFFu;
+    const uint32_t n2 = __builtin_amdgcn_alignbit(w2, w1, 16) & 0xFFFFFFu;
+    const uint32_t n3 = w2 >> 8;
+    a = ((uint64_t)number_f32_bits(n1) << 32) | number_f32_bits(n0);
+    b = ((uint64_t)number_f32_bits(n3) << 32) | number_f32_bits(n2);
   } else {
     double u1, u2;
     pair_f64(w0, w1, w2, u1, u2);

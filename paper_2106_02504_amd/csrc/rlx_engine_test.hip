@@ -52,6 +52,9 @@ __global__ __launch_bounds__(ENGINE_BLOCK) void k_engine(rlx_state* __restrict__
       double v;
       if constexpr (mode == 3) {
         v = rlx_engine_next_normal(e, t);
+      } else if constexpr (mode == 7) {
+        const float2 f = rlx_engine_next_f32x2(e, t);
+        __builtin_memcpy(&v, &f, 8);
       } else if constexpr (mode == 4) {
         const uint64_t u = rlx_engine_next_u48(e, t);
         __builtin_memcpy(&v, &u, 8);
@@ -69,7 +72,7 @@ __global__ __launch_bounds__(ENGINE_BLOCK) void k_engine(rlx_state* __restrict__
 extern "C" int rlx_test_engine(rlx_state* states, uint64_t n, uint64_t count, double* out, uint32_t mode,
                                uint32_t p, void* stream) {
   if (n == 0) return RLX_OK;
-  if (!states || !out || mode > 6) return RLX_EINVAL;
+  if (!states || !out || mode > 7) return RLX_EINVAL;
   if ((reinterpret_cast<uintptr_t>(states) & 15) != 0 || (reinterpret_cast<uintptr_t>(out) & 7) != 0)
     return RLX_EINVAL;
   if (n > RLX_MAX_STREAMS || (mode != 5 && count > UINT64_MAX / 8 / n)) return RLX_EINVAL;
@@ -83,7 +86,7 @@ extern "C" int rlx_test_engine(rlx_state* states, uint64_t n, uint64_t count, do
 #define RLX_ENGINE_MODE(M) \
   case M: k_engine<M><<<(unsigned)blocks, ENGINE_BLOCK, 0, s>>>(states, n, count, out, t); break;
     RLX_ENGINE_MODE(0) RLX_ENGINE_MODE(1) RLX_ENGINE_MODE(2) RLX_ENGINE_MODE(3) RLX_ENGINE_MODE(4)
-    RLX_ENGINE_MODE(5) RLX_ENGINE_MODE(6)
+    RLX_ENGINE_MODE(5) RLX_ENGINE_MODE(6) RLX_ENGINE_MODE(7)
 #undef RLX_ENGINE_MODE
   }
   return hipGetLastError() == hipSuccess ? RLX_OK : RLX_EHIP;

@@ -74,3 +74,22 @@ def test_invalid_arguments_fail_before_any_device_work(rlx):
     assert lib.rlx_generate_f64(None, 0, 10, None, 2048, None) == 0
     assert lib.rlx_generate_u64(None, 5, 0, None, 2048, None) == 0
     assert lib.rlx_skip(None, 0, None, 0, 2048, None) == 0
+
+
+def test_other_widths_argument_checks(rlx):
+    lib = rlx.lib()
+    v = ctypes.c_void_p
+    # float32 draws come in pairs: odd counts are rejected, even with n = 0
+    assert lib.rlx_generate_f32(v(16), 5, 7, v(16), 2048, None) == 1
+    assert lib.rlx_generate_f32(None, 0, 3, None, 2048, None) == 1
+    assert lib.rlx_generate_f32(None, 0, 4, None, 2048, None) == 0
+    assert lib.rlx_generate_f32(v(16), 5, 10, v(12), 2048, None) == 1      # out not 8-byte aligned
+    assert lib.rlx_generate_f32(v(16), 1, 2 * ((1 << 35) + 1), v(16), 2048, None) == 1
+    assert lib.rlx_generate_f32(v(16), 5, 10, v(16), 23, None) == 1
+    # legacy doubles: same checks as the 48-bit doubles
+    assert lib.rlx_generate_f64_lcg52(None, 5, 10, None, 2048, None) == 1
+    assert lib.rlx_generate_f64_lcg52(v(16), 5, 10, v(12), 2048, None) == 1
+    assert lib.rlx_generate_f64_lcg52(v(16), 1 << 32, 1, v(16), 2048, None) == 1
+    assert lib.rlx_generate_f64_lcg52(None, 0, 10, None, 2048, None) == 0
+    assert lib.rlx_plan_generate_f32(None, v(16), v(16), None) == 1
+    assert lib.rlx_test_engine(v(16), 5, 10, v(16), 8, 2048, None) == 1
