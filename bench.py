@@ -112,18 +112,24 @@ def sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel sources."""
+def measured_counters(kernel: str) -> dict:
+    """The committed rocprofv3 counter summary of `kernel` (HBM bytes, VALU
+    instructions per launch), if it was taken on the current kernel sources;
+    otherwise an empty dict."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         doc = json.load(open(path))
     except (OSError, ValueError):
-        return None
+        return {}
     ent = doc.get(kernel)
     if not ent or ent.get("sources_sha") != sources_sha():
-        return None
-    return ent.get("hbm_bytes_per_launch")
+        return {}
+    return ent
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary, or None."""
+    return measured_counters(kernel).get("hbm_bytes_per_launch")
 
 
 def timed(fn, stream, steps, warmup, torch):
@@ -365,6 +371,20 @@ def main() -> int:
                     "note": "27 32x32->64 multiply-adds per double (schoolbook 18x18 words per 12 doubles) "
                             "against one full-rate 32-bit VALU op per lane per cycle"}
 
+    # VALU issue: instructions the kernel executes per launch (SQ_INSTS_VALU
+    # from the committed counter run, same workload) against what the SIMDs
+    # can issue in the measured kernel time: one wave64 VALU instruction per
+    # 4 cycles on each of 1024 SIMDs at 2.4 GHz
+    valu_insts = measured_counters("k_generate_f64_many_streams").get("valu_insts_per_launch")
+    valu_issue = None
+    if valu_insts:
+        cap = 1024 * gen_ms * 1e-3 * 2.4e9 / 4
+        valu_issue = {"insts_per_launch": valu_insts, "issue_capacity_at_2.4GHz": round(cap),
+                      "frac": round(valu_insts / cap, 4),
+                      "note": "executed VALU instructions (rocprofv3 SQ_INSTS_VALU, profiles/traffic.json) over "
+                              "the issue capacity of 1024 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction in the "
+                              "measured kernel time; counts executed work, not algorithmic work"}
+
     legs = {}
     if "u64" in wanted:
         outu = torch.empty((N_STREAMS, DRAWS), dtype=torch.int64, device=dev)
@@ -476,6 +496,7 @@ def main() -> int:
         "bit_exact": bit_exact,
         "roofline": roofline,
         "roofline_alu": roofline_alu,
+        "valu_issue": valu_issue,
         "cpu_baseline": cpu,
         "legs": legs,
         "kernel_sources_sha": sources_sha(),

@@ -428,6 +428,28 @@ class Plan:
             pass
 
 
+def batch(states: torch.Tensor, requests, out: torch.Tensor | None = None, lanes: int = 32,
+          seg_blocks: int = 4096, dtype: torch.dtype = torch.float64) -> torch.Tensor:
+    """One-shot batched generation: plan `requests` (REQUEST_DTYPE, e.g. from
+    requests_array), run the persistent launch and free the plan (which
+    synchronises the device).  dtype float64, int64 (the 48-bit values) or
+    float32 (two floats per position).  `out` is allocated to the requests'
+    extent when None.  For repeated batches keep a Plan, whose launches can be
+    captured in a HIP graph, or use serve.Server."""
+    per = {torch.float64: 1, torch.int64: 1, torch.float32: 2}
+    if dtype not in per:
+        raise ValueError("dtype must be float64, int64 or float32")
+    plan = Plan(requests, lanes=lanes, seg_blocks=seg_blocks, device=states.device)
+    try:
+        if out is None:
+            out = torch.empty(per[dtype] * plan.extent, dtype=dtype, device=states.device)
+        {torch.float64: plan.generate_f64, torch.int64: plan.generate_u64,
+         torch.float32: plan.generate_f32}[dtype](states, out)
+    finally:
+        plan.close()
+    return out
+
+
 def plan_dry_run(requests, lanes: int = 8, seg_blocks: int = 2048):
     """Host-only planner run (no GPU): returns (segments [k, 6] uint64 array
     in launch order, n_items, total values); see rlx_plan_dry_run."""

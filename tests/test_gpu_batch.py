@@ -88,6 +88,30 @@ def test_batch_f64_equals_plain_kernel():
     plan.close()
 
 
+def test_one_shot_batch_helper_all_dtypes():
+    # rlx.batch plans, runs and frees in one call; the three output forms
+    # agree with each other and with the oracle windows
+    rng = random.Random(31)
+    recs, req = small_batch(rng, n_req=40, max_count=2000)
+    st = records_to_tensor(recs)
+    u = rlx.batch(st, req, dtype=torch.int64)
+    f = rlx.batch(st, req, lanes=8, seg_blocks=64)
+    h = rlx.batch(st, req, lanes=64, seg_blocks=16, dtype=torch.float32)
+    total = int(req["count"].sum())
+    assert u.shape == (total,) and f.shape == (total,) and h.shape == (2 * total,)
+    assert torch.equal(u.to(torch.float64) * 2.0 ** -48, f)
+    lo = (h[0::2].to(torch.float64) * 2.0 ** 24).to(torch.int64)
+    hi = (h[1::2].to(torch.float64) * 2.0 ** 24).to(torch.int64)
+    assert torch.equal(lo + (hi << 24), u)
+    got = u.cpu().numpy()
+    exp = expected(recs, req)
+    for k in range(0, len(req), 3):
+        o, c = int(req["out_offset"][k]), int(req["count"][k])
+        assert got[o:o + c].tolist() == exp[k], k
+    with pytest.raises(ValueError):
+        rlx.batch(st, req, dtype=torch.float16)
+
+
 def test_plan_update_and_graph_replays():
     rng = random.Random(11)
     p = 404
