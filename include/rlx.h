@@ -78,6 +78,7 @@ enum {
  * one device holds for a single record). */
 #define RLX_MAX_STREAMS 0xFFFFFFFFull
 #define RLX_MAX_COUNT   (1ull << 35)
+#define RLX_MAX_LANES   65536u   /* lanes per record a generate call may use */
 /* Largest segment length of a batch plan, in generator steps. */
 #define RLX_MAX_SEG_BLOCKS (1ull << 26)
 
@@ -238,7 +239,8 @@ int rlx_import_ranlux(rlx_state *states, uint64_t n, const uint64_t *packed,
  * advancing by the launch-uniform multiplier A_p^G), and their values are
  * staged through LDS so that stores write contiguous runs of the output row.
  * By default G is picked from n and count (rlx_lanes_per_stream reports the
- * pick); rlx_set_lanes_per_stream(G) forces a power of two G <= 4096 for all
+ * pick); rlx_set_lanes_per_stream(G) forces a power of two G <=
+ * RLX_MAX_LANES for all
  * later calls in the process (0 restores the automatic pick).  The values
  * produced never depend on G. */
 int rlx_set_lanes_per_stream(uint32_t lanes);

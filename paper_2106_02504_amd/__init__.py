@@ -320,7 +320,7 @@ def generate_f64_trace(states: torch.Tensor, count: int, p: int):
 
 def set_lanes_per_stream(lanes: int) -> None:
     """Force G lanes per record for later generate calls (power of two
-    <= 4096); 0 restores the automatic choice.  Values never depend on G."""
+    <= 65536); 0 restores the automatic choice.  Values never depend on G."""
     _check(lib().rlx_set_lanes_per_stream(lanes), "rlx_set_lanes_per_stream")
 
 

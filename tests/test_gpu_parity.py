@@ -348,7 +348,7 @@ def lanes_reset():
     rlx.set_lanes_per_stream(0)
 
 
-@pytest.mark.parametrize("G", (1, 2, 4, 8, 16, 32, 64, 128, 1024, 4096))
+@pytest.mark.parametrize("G", (1, 2, 4, 8, 16, 32, 64, 128, 1024, 4096, 16384, 65536))
 def test_lanes_per_stream_bit_identical(G, lanes_reset):
     rng = random.Random(200 + G)
     p = 218

@@ -93,3 +93,26 @@ def test_other_widths_argument_checks(rlx):
     assert lib.rlx_generate_f64_lcg52(None, 0, 10, None, 2048, None) == 0
     assert lib.rlx_plan_generate_f32(None, v(16), v(16), None) == 1
     assert lib.rlx_test_engine(v(16), 5, 10, v(16), 8, 2048, None) == 1
+
+
+def test_automatic_lanes_per_stream(rlx):
+    # host-only pick of lanes per record: powers of two within the launch
+    # and step limits; more lanes for few streams, whole waves otherwise
+    lib = rlx.lib()
+    pick = rlx.lanes_per_stream
+    assert pick(65536, 4096) == 16            # the many-streams shape
+    assert pick(1, 1 << 20) == 65536          # one long stream fills the chip
+    assert pick(64, 1 << 20) == 4096          # 16 steps per lane once past 2^16 lanes
+    assert pick(1 << 20, 4096) == 1
+    assert pick(1, 11) == 1 and pick(1, 12) == 2
+    for n in (1, 3, 100, 5000, 1 << 16, 1 << 21):
+        for count in (1, 12, 1000, 1 << 16, 1 << 22):
+            g = pick(n, count)
+            steps = count // 12 + 1
+            assert g & (g - 1) == 0 and 1 <= g <= 65536
+            assert g == 1 or (n * g <= 1 << 20 and steps // g >= 1)
+            assert g == 1 or steps // g >= 16 or n * g <= 1 << 16
+    # the override: powers of two up to 65536, 0 restores the automatic pick
+    assert lib.rlx_set_lanes_per_stream(65536) == 0 and pick(65536, 4096) == 65536
+    assert lib.rlx_set_lanes_per_stream(131072) == 1 and lib.rlx_set_lanes_per_stream(48) == 1
+    assert lib.rlx_set_lanes_per_stream(0) == 0 and pick(65536, 4096) == 16
