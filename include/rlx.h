@@ -218,7 +218,8 @@ int rlx_skip_values(rlx_state *states, uint64_t n, const uint64_t *values,
  * RANLUX numbers of the current step (oldest in the least significant 24
  * bits), carry[i] = the RANLUX carry c = X - D + floor(D / 2^336) (0 or 1),
  * pos[i] = the record's pos (may be NULL).  Records with X >= m are flagged
- * RLX_ERR_BAD_X and their outputs left unwritten. */
+ * RLX_ERR_BAD_X and their outputs left unwritten.  packed must be 8-byte,
+ * carry and pos 4-byte aligned (RLX_EINVAL otherwise). */
 int rlx_export_ranlux(const rlx_state *states, uint64_t n, uint64_t *packed,
                       uint32_t *carry, uint32_t *pos, void *stream);
 
@@ -229,7 +230,8 @@ int rlx_export_ranlux(const rlx_state *states, uint64_t n, uint64_t *packed,
  * number 2^24 - 1 and carry 1, X = m) and exporting X gives back (D, c);
  * otherwise the record is left unchanged and RLX_ERR_NOT_CANONICAL (or
  * RLX_ERR_BAD_POS for pos > 11) is flagged.  Any SWB state becomes canonical
- * after 24 steps of the subtract-with-borrow recurrence. */
+ * after 24 steps of the subtract-with-borrow recurrence.  Alignment as for
+ * rlx_export_ranlux. */
 int rlx_import_ranlux(rlx_state *states, uint64_t n, const uint64_t *packed,
                       const uint32_t *carry, const uint32_t *pos, uint32_t p,
                       void *stream);
@@ -256,7 +258,9 @@ uint32_t rlx_lanes_per_stream(uint64_t n, uint64_t count);
 /* One request: values start, start + 1, ..., start + count - 1 of the stream
  * whose current position is record `state` (position 0 = the record's next
  * value), written to out[out_offset .. out_offset + count).  p must be the
- * record's luxury level. */
+ * record's luxury level.  The library does not know the length of the
+ * states array a plan will run on: the caller guarantees that every
+ * request's `state` indexes a record of it (the Python binding checks). */
 typedef struct rlx_request {
     uint64_t state;       /* index into the states array */
     uint64_t start;       /* first value, counted from the record's position */

@@ -199,8 +199,18 @@ def export_ranlux(states: torch.Tensor):
 def import_ranlux(states: torch.Tensor, packed: torch.Tensor, carry: torch.Tensor, p: int,
                   pos: torch.Tensor | None = None) -> torch.Tensor:
     """Records from RANLUX-form states (canonical ones only; others are
-    flagged in the error word and left unchanged)."""
+    flagged in the error word and left unchanged): packed [n, 9] int64,
+    carry [n] and pos [n] (optional) int32, on the states' device."""
     n = _need_states(states)
+
+    def need(t, shape, dtypes, what):
+        if (t.dtype not in dtypes or tuple(t.shape) != shape or not t.is_contiguous()
+                or t.device != states.device):
+            raise ValueError(f"{what} must be a contiguous {shape} tensor on the states' device")
+    need(packed, (n, 9), (torch.int64, torch.uint64), "packed")
+    need(carry, (n,), (torch.int32, torch.uint32), "carry")
+    if pos is not None:
+        need(pos, (n,), (torch.int32, torch.uint32), "pos")
     with torch.cuda.device(states.device):
         _check(lib().rlx_import_ranlux(states.data_ptr(), n, packed.data_ptr(), carry.data_ptr(), _ptr(pos), p,
                                        _stream()), "rlx_import_ranlux")
@@ -365,23 +375,27 @@ class Plan:
             _check(lib().rlx_plan_create(ctypes.byref(self._h), req.ctypes.data, req.shape[0], lanes, seg_blocks,
                                          capacity_segments, _stream()), "rlx_plan_create")
         self.lanes, self.seg_blocks = lanes, seg_blocks
-        self.extent = self._extent(req)
+        self.extent, self.records = self._extent(req)
 
     @staticmethod
-    def _extent(req) -> int:
-        """Output elements the requests need: max of out_offset + count (the
-        library accepted them, so these sums do not overflow)."""
+    def _extent(req) -> tuple[int, int]:
+        """(output elements, records) the requests need: max of out_offset +
+        count and of state + 1 over requests with count > 0 (the library
+        accepted them, so these sums do not overflow)."""
         live = req[req["count"] > 0]
-        return int((live["out_offset"] + live["count"]).max()) if live.shape[0] else 0
+        if not live.shape[0]:
+            return 0, 0
+        return int((live["out_offset"] + live["count"]).max()), int(live["state"].max()) + 1
 
     def update(self, requests) -> None:
         req = _np.ascontiguousarray(requests, dtype=REQUEST_DTYPE)
         with torch.cuda.device(self.device):
             _check(lib().rlx_plan_update(self._h, req.ctypes.data, req.shape[0], _stream()), "rlx_plan_update")
-        self.extent = self._extent(req)
+        self.extent, self.records = self._extent(req)
 
     def _check_out(self, states: torch.Tensor, out: torch.Tensor, dtype: torch.dtype, per_value: int) -> None:
-        _need_states(states)
+        if _need_states(states) < self.records:
+            raise ValueError(f"the requests read record {self.records - 1}; states holds {states.shape[0]}")
         if out.dtype != dtype or not out.is_contiguous() or out.device != states.device:
             raise ValueError(f"out must be a contiguous {dtype} tensor on the states' device")
         if out.numel() < per_value * self.extent:

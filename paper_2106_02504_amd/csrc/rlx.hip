@@ -731,6 +731,7 @@ int rlx_export_ranlux(const rlx_state* states, uint64_t n, uint64_t* packed, uin
                       void* stream) {
   if (n == 0) return RLX_OK;
   if (!states || !packed || !carry || !aligned(states, 16) || !aligned(packed, 8)) return RLX_EINVAL;
+  if (!aligned(carry, 4) || (pos && !aligned(pos, 4))) return RLX_EINVAL;
   dim3 grid;
   if (!grid_for(n, &grid)) return RLX_EINVAL;
   hipStream_t s = as_stream(stream);
@@ -746,6 +747,7 @@ int rlx_import_ranlux(rlx_state* states, uint64_t n, const uint64_t* packed, con
   if (n == 0) return RLX_OK;
   if (!states || !packed || !carry || !valid_p(p) || !aligned(states, 16) || !aligned(packed, 8))
     return RLX_EINVAL;
+  if (!aligned(carry, 4) || (pos && !aligned(pos, 4))) return RLX_EINVAL;
   dim3 grid;
   if (!grid_for(n, &grid)) return RLX_EINVAL;
   hipStream_t s = as_stream(stream);

@@ -182,8 +182,19 @@ def test_plan_errors():
     plan2 = rlx.Plan(rlx.requests_array([0], [0], [12], 24), lanes=4, seg_blocks=1, capacity_segments=2)
     with pytest.raises(rlx.RlxError):
         plan2.update(rlx.requests_array([0], [0], [1000], 24))
+    # the binding refuses a launch whose requests read past the records or
+    # write past `out` (the library itself cannot know those lengths)
+    plan3 = rlx.Plan(rlx.requests_array([0, 1], [0, 0], [5, 5], 24), lanes=4, seg_blocks=2)
+    with pytest.raises(ValueError):
+        plan3.generate_u64(st, torch.empty(10, dtype=torch.int64, device=DEV))
+    st2 = make_records([(1, 24), (2, 24)])
+    with pytest.raises(ValueError):
+        plan3.generate_u64(st2, torch.empty(9, dtype=torch.int64, device=DEV))
+    out3 = plan3.generate_u64(st2, torch.empty(10, dtype=torch.int64, device=DEV))
+    assert out3.cpu().tolist() == O.window(O.seed(1, 24), 24, 0, 5) + O.window(O.seed(2, 24), 24, 0, 5)
     plan.close()
     plan2.close()
+    plan3.close()
 
 
 def test_batch_workload_sampled():

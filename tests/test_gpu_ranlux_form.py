@@ -101,3 +101,15 @@ def test_skip_values_equals_drawing():
     rlx.skip_values(st1, 29, p)
     rlx.generate_u64(st2, 29, p)
     assert torch.equal(st1, st2)
+
+
+def test_import_checks_tensor_shapes():
+    st = rlx.new_states(4)
+    packed = torch.zeros((4, 9), dtype=torch.int64, device=DEV)
+    carry = torch.zeros(4, dtype=torch.int32, device=DEV)
+    with pytest.raises(ValueError):
+        rlx.import_ranlux(st, packed[:3], carry, 24)
+    with pytest.raises(ValueError):
+        rlx.import_ranlux(st, packed, carry.to(torch.int64), 24)
+    with pytest.raises(ValueError):
+        rlx.import_ranlux(st, packed, carry, 24, pos=torch.zeros(5, dtype=torch.int32, device=DEV))

@@ -116,3 +116,15 @@ def test_automatic_lanes_per_stream(rlx):
     assert lib.rlx_set_lanes_per_stream(65536) == 0 and pick(65536, 4096) == 65536
     assert lib.rlx_set_lanes_per_stream(131072) == 1 and lib.rlx_set_lanes_per_stream(48) == 1
     assert lib.rlx_set_lanes_per_stream(0) == 0 and pick(65536, 4096) == 16
+
+
+def test_ranlux_form_argument_checks(rlx):
+    lib = rlx.lib()
+    v = ctypes.c_void_p
+    assert lib.rlx_export_ranlux(v(16), 3, v(16), v(2), None, None) == 1      # carry not 4-byte aligned
+    assert lib.rlx_export_ranlux(v(16), 3, v(16), v(16), v(6), None) == 1     # pos not 4-byte aligned
+    assert lib.rlx_import_ranlux(v(16), 3, v(16), v(2), None, 24, None) == 1
+    assert lib.rlx_import_ranlux(v(16), 3, v(16), v(16), v(6), 24, None) == 1
+    assert lib.rlx_import_ranlux(v(16), 3, v(12), v(16), None, 24, None) == 1  # packed not 8-byte aligned
+    assert lib.rlx_import_ranlux(v(16), 3, v(16), v(16), None, 23, None) == 1
+    assert lib.rlx_export_ranlux(None, 0, None, None, None, None) == 0
