@@ -408,7 +408,7 @@ def main() -> int:
         def step_1():
             rlx.init_streams(st1, P, id0=1)
             rlx.generate_f64_trace(st1, 1 << 20, P)
-        dt = timed(step_1, stream, 5, 2, torch)
+        dt = timed(step_1, stream, 50, 10, torch)
         legs["single"] = {"value": (1 << 20) / dt, "unit": "doubles/s", "ms_per_step": dt * 1e3,
                           "lanes_per_stream": rlx.lanes_per_stream(1, 1 << 20),
                           "workload": "1 stream (id 1), p=2048, 2^20 doubles + state after each step"}

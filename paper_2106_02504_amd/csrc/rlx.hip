@@ -1,7 +1,7 @@
 // rlx.hip -- RANLUX++ kernels for gfx950 and the C ABI of librlx.so.
 //
 // Kernels (one lane per stream record unless noted):
-//   k_tab_base / k_tab_fill / k_tab_fold   per-luxury-level constant tables
+//   k_tab_base / k_tab_fill / k_tab_fold / k_tab_w8   per-luxury-level tables
 //   k_init                                 seeding        (section 2.4)
 //   k_skip                                 skip-ahead     (section 2.4)
 //   k_generate<U64|F64|NORMAL|F32, trace, LGS> draw values (sections 2.1-2.3)
@@ -67,6 +67,22 @@ __global__ __launch_bounds__(64) void k_tab_fill(uint32_t* __restrict__ T) {
   store_words(T + ((size_t)i * TAB_COLS + j) * NW, r);
 }
 
+// W[i][j] = T[r][j mod 16] T[r + 1][j / 16] with r = 2i for the skip rows
+// (i < 8) and r = 24 + 2 (i - 8) for the seed rows: A_p^(j 256^i) from two
+// hexadecimal windows.  One lane per entry.
+__global__ __launch_bounds__(64) void k_tab_w8(const uint32_t* __restrict__ T, uint32_t* __restrict__ W) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= W8_ROWS * W8_COLS) return;
+  const int i = t / W8_COLS;
+  const uint32_t j = (uint32_t)(t % W8_COLS);
+  const int r = i < W8_SEED_ROW0 ? 2 * i : SEED_ROW0 + 2 * (i - W8_SEED_ROW0);
+  uint32_t a[NW], b[NW], y[NW];
+  load_words(T + ((size_t)r * TAB_COLS + (j & 15u)) * NW, a);
+  load_words(T + ((size_t)(r + 1) * TAB_COLS + (j >> 4)) * NW, b);
+  mulmod_generic(a, b, y);
+  store_words(W + (size_t)t * NW, y);
+}
+
 // C_g[j] = A_p^(2^g) 2^(o_j) mod m: block g (g < 64) builds the folded
 // multiplier of a step by 2^g generator steps, one lane per row j.  A_p^(2^g)
 // is a single entry of T: 2^g = v 16^i with v in {1, 2, 4, 8}.
@@ -86,19 +102,21 @@ __global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T,
 // ---------------------------------------------------------------------------
 // seeding and skipping (section 2.4)
 
+// X = A_p^(2^96 id) from 1: the product of the seed windows of the non-zero
+// bytes of id (the first one copied, not multiplied).
 __global__ __launch_bounds__(BLOCK) void k_init(rlx_state* __restrict__ st, uint64_t n,
                                                 const uint64_t* __restrict__ ids, uint64_t id0,
-                                                uint32_t p, const uint32_t* __restrict__ T) {
+                                                uint32_t p, const uint32_t* __restrict__ W) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const uint64_t id = ids ? ids[i] : id0 + i;
   uint32_t x[NW];
   set_one(x);
   bool first = true;
-  for (int nib = 0; nib < 16 && (id >> (4 * nib)) != 0; ++nib) {
-    const uint32_t v = (uint32_t)(id >> (4 * nib)) & 15u;
+  for (int b = 0; b < 8 && (id >> (8 * b)) != 0; ++b) {
+    const uint32_t v = (uint32_t)(id >> (8 * b)) & 255u;
     if (v == 0) continue;
-    const uint32_t* e = T + ((size_t)(SEED_ROW0 + nib) * TAB_COLS + v) * NW;
+    const uint32_t* e = W + ((size_t)(W8_SEED_ROW0 + b) * W8_COLS + v) * NW;
     uint32_t y[NW];
     load_words(e, y);
     if (first) {
@@ -115,7 +133,7 @@ __global__ __launch_bounds__(BLOCK) void k_init(rlx_state* __restrict__ st, uint
 // many values (pos + v = 12 k + pos', k steps, new pos').
 __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint64_t n,
                                                 const uint64_t* __restrict__ steps, uint64_t steps0,
-                                                uint32_t p, const uint32_t* __restrict__ T,
+                                                uint32_t p, const uint32_t* __restrict__ W,
                                                 uint32_t* __restrict__ err, int by_values) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -133,7 +151,7 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
     k = v / FIELDS + r / FIELDS;
     pos = r % FIELDS;
   }
-  skip_windows(x, k, T);
+  skip_windows(x, k, W);
   store_record(st, i, x, pos, sp);
 }
 
@@ -145,7 +163,7 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
 // Block t of a record is the t-th LCG state visited (t = 0 is the state on
 // entry, t = nadv the state after the last advance); the value with output
 // index j is field (pos + j) mod 12 of block (pos + j) / 12.  Lane l of a
-// record starts at block l (X_l = A^l X_0, by folded steps) and then takes
+// record starts at block l (X_l = A^l X_0, by windows) and then takes
 // blocks l + G, l + 2G, ... with the folded multiplier of A^G, so the G lanes
 // of a record hold G consecutive blocks at every iteration.
 //
@@ -161,7 +179,7 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
                                                     uint64_t count, uint64_t* __restrict__ out,
                                                     uint64_t* __restrict__ trace, uint64_t trace_steps,
                                                     const uint32_t* __restrict__ ctabs,
-                                                    const uint32_t* __restrict__ T, uint32_t lg,
+                                                    const uint32_t* __restrict__ W, uint32_t lg,
                                                     uint32_t p, uint32_t* __restrict__ err,
                                                     int force_general) {
   // Per-lane state kept across the loop is x plus four 32-bit words (record
@@ -196,7 +214,7 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
 
   // lane l starts at block l: X_l = A^l X_0 (bits 6 and up of l are the
   // same for the whole wave)
-  if (STAGED) skip_windows(x, l, T);
+  if (STAGED) skip_windows(x, l, W);
   const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * FOLD_ROW_WORDS;
 
   for (uint32_t k = 0;; ++k) {
@@ -258,7 +276,7 @@ template <int LGS>
 __global__ __launch_bounds__(BLOCK) void k_generate_lcg52(rlx_state* __restrict__ st, uint32_t n, uint64_t count,
                                                           double* __restrict__ out,
                                                           const uint32_t* __restrict__ ctabs,
-                                                          const uint32_t* __restrict__ T, uint32_t lg, uint32_t p,
+                                                          const uint32_t* __restrict__ W, uint32_t lg, uint32_t p,
                                                           uint32_t* __restrict__ err) {
   constexpr uint32_t gs = 1u << LGS;  // lanes of a record inside one wave
   __shared__ double stage[BLOCK * LCG52_VALUES];
@@ -283,7 +301,7 @@ __global__ __launch_bounds__(BLOCK) void k_generate_lcg52(rlx_state* __restrict_
     pos = 0;
   }
   const uint32_t nadv = (uint32_t)((pos + count) / LCG52_VALUES);
-  skip_windows(x, l, T);
+  skip_windows(x, l, W);
   const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * FOLD_ROW_WORDS;
   const uint32_t ls = l & (gs - 1);
   double* const slot = stage + (size_t)threadIdx.x * LCG52_VALUES;
@@ -503,13 +521,20 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
     (void)hipFree(t.T);
     return RLX_ENOMEM;
   }
+  if (hipMalloc(&t.W, W8_WORDS * sizeof(uint32_t)) != hipSuccess) {
+    (void)hipFree(t.T);
+    (void)hipFree(t.C);
+    return RLX_ENOMEM;
+  }
   k_tab_base<<<1, 64, 0, s>>>(t.T, p);
   const int fill = TAB_ROWS * (TAB_COLS - 2);
   k_tab_fill<<<(fill + 63) / 64, 64, 0, s>>>(t.T);
   k_tab_fold<<<FOLD_G, 64, 0, s>>>(t.T, t.C);
+  k_tab_w8<<<(W8_ROWS * W8_COLS + 63) / 64, 64, 0, s>>>(t.T, t.W);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     (void)hipFree(t.T);
     (void)hipFree(t.C);
+    (void)hipFree(t.W);
     return RLX_EHIP;
   }
   g_tables[key] = t;
@@ -530,7 +555,7 @@ std::atomic<uint32_t> g_lanes_override{0};
 // the launch stays within sixteen waves per SIMD (2^20 lanes on 256 CUs) and
 // every lane still takes at least 16 generator steps -- or, while the launch
 // has fewer lanes than one wave per SIMD (2^16), at least one step.  A lane
-// pays one windowed multiplication per hexadecimal digit of its index at
+// pays one windowed multiplication per non-zero byte of its index at
 // start-up, so G trades start-up work against parallelism and against the
 // length of the contiguous runs each store instruction writes (16 G bytes
 // per record).  On the many-streams shape G = 16 measured fastest; a single
@@ -592,7 +617,7 @@ int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint
   const uint32_t lgs = lg < 6 ? lg : 6;
 #define RLX_GEN(L)                                                                                    \
   case L:                                                                                             \
-    k_generate<K, TRACE, L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, trace, trace_steps, t.C, t.T, lg, p, \
+    k_generate<K, TRACE, L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, trace, trace_steps, t.C, t.W, lg, p, \
                                                      err, force_general);                             \
     break;
   switch (lgs) {
@@ -618,7 +643,7 @@ int generate_lcg52_impl(rlx_state* states, uint64_t n, uint64_t count, double* o
   const uint32_t lgs = lg < 6 ? lg : 6;
 #define RLX_GEN52(L)                                                                                  \
   case L:                                                                                             \
-    k_generate_lcg52<L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, out, t.C, t.T, lg, p, err); \
+    k_generate_lcg52<L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, out, t.C, t.W, lg, p, err); \
     break;
   switch (lgs) {
     RLX_GEN52(0) RLX_GEN52(1) RLX_GEN52(2) RLX_GEN52(3) RLX_GEN52(4) RLX_GEN52(5) RLX_GEN52(6)
@@ -687,7 +712,7 @@ int rlx_init_streams(rlx_state* states, uint64_t n, const uint64_t* ids, uint64_
   Tables t;
   int rc = tables(p, s, &t);
   if (rc) return rc;
-  k_init<<<grid, BLOCK, 0, s>>>(states, n, ids, id0, p, t.T);
+  k_init<<<grid, BLOCK, 0, s>>>(states, n, ids, id0, p, t.W);
   return launch_status();
 }
 
@@ -705,7 +730,7 @@ int rlx_skip(rlx_state* states, uint64_t n, const uint64_t* steps, uint64_t step
   uint32_t* err;
   rc = error_word(s, &err);
   if (rc) return rc;
-  k_skip<<<grid, BLOCK, 0, s>>>(states, n, steps, steps0, p, t.T, err, 0);
+  k_skip<<<grid, BLOCK, 0, s>>>(states, n, steps, steps0, p, t.W, err, 0);
   return launch_status();
 }
 
@@ -723,7 +748,7 @@ int rlx_skip_values(rlx_state* states, uint64_t n, const uint64_t* values, uint6
   uint32_t* err;
   rc = error_word(s, &err);
   if (rc) return rc;
-  k_skip<<<grid, BLOCK, 0, s>>>(states, n, values, values0, p, t.T, err, 1);
+  k_skip<<<grid, BLOCK, 0, s>>>(states, n, values, values0, p, t.W, err, 1);
   return launch_status();
 }
 

@@ -64,7 +64,7 @@ struct Header {
   uint32_t n_items;
   uint32_t pad[2];
   const uint32_t* C[MAX_LEVELS];  // folded multipliers A^(2^g) of each level
-  const uint32_t* T[MAX_LEVELS];  // window tables A^(j 16^i) of each level
+  const uint32_t* W[MAX_LEVELS];  // 8-bit window tables A^(j 256^i) of each level
   uint32_t p[MAX_LEVELS];
 };
 
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ s
     const Item item = items[it];
     const uint32_t slot = __builtin_amdgcn_readfirstlane(item.slot);
     const uint32_t* __restrict__ ctabs = hdr->C[slot];
-    const uint32_t* __restrict__ wtabs = hdr->T[slot];
+    const uint32_t* __restrict__ wtabs = hdr->W[slot];
     const uint32_t p = __builtin_amdgcn_readfirstlane(hdr->p[slot]);
     bool active = team < item.nseg;
     uint32_t si = item.seg0 + team;
@@ -276,7 +276,7 @@ int upload(rlx_plan* plan, const Planned& pl, hipStream_t s) {
     const int rc = tables(pl.ps[k], s, &t);
     if (rc) return rc;
     hd.C[k] = t.C;
-    hd.T[k] = t.T;
+    hd.W[k] = t.W;
     hd.p[k] = pl.ps[k];
   }
   // the previous upload must have left the staging buffers
