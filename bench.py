@@ -134,6 +134,18 @@ def measured_traffic(kernel: str):
     return measured_counters(kernel).get("hbm_bytes_per_launch")
 
 
+def device_info(torch, dev) -> dict:
+    """What the runtime reports for the GPU the bench ran on (the roofline
+    peaks use the published figures: 256 CUs, 2.4 GHz, 8 TB/s)."""
+    pr = torch.cuda.get_device_properties(dev)
+    info = {"name": pr.name, "compute_units": pr.multi_processor_count,
+            "memory_gib": round(pr.total_memory / 2 ** 30, 1)}
+    for attr in ("gcnArchName", "clock_rate", "L2_cache_size"):
+        if hasattr(pr, attr):
+            info[attr] = getattr(pr, attr)
+    return info
+
+
 def timed(fn, stream, steps, warmup, torch):
     for _ in range(warmup):
         fn()
@@ -332,8 +344,11 @@ def main() -> int:
     out = torch.empty((N_STREAMS, DRAWS), dtype=torch.float64, device=dev)
 
     ev = []
+    ev_init = []
 
     def step():
+        i0 = torch.cuda.Event(enable_timing=True)
+        i0.record(stream)
         rlx.init_streams(st, P, id0=0)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
@@ -341,17 +356,20 @@ def main() -> int:
         rlx.generate_f64(st, DRAWS, P, out=out)
         e1.record(stream)
         ev.append((e0, e1))
+        ev_init.append((i0, e0))
 
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
     ev.clear()
+    ev_init.clear()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / args.steps
     gen_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    init_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_init]))
     total = N_STREAMS * DRAWS
     value = total / wall
 
@@ -409,8 +427,14 @@ def main() -> int:
             rlx.init_streams(st1, P, id0=1)
             rlx.generate_f64_trace(st1, 1 << 20, P)
         dt = timed(step_1, stream, 50, 10, torch)
+        # the same stream in one lane: the latency of a generator step
+        rlx.set_lanes_per_stream(1)
+        dt1 = timed(step_1, stream, 1, 1, torch)
+        rlx.set_lanes_per_stream(args.lanes)
+        steps1 = (1 << 20) // 12 + 1
         legs["single"] = {"value": (1 << 20) / dt, "unit": "doubles/s", "ms_per_step": dt * 1e3,
                           "lanes_per_stream": rlx.lanes_per_stream(1, 1 << 20),
+                          "one_lane_ms": dt1 * 1e3, "one_lane_us_per_generator_step": dt1 * 1e6 / steps1,
                           "workload": "1 stream (id 1), p=2048, 2^20 doubles + state after each step"}
     if "skip" in wanted:
         import workloads
@@ -500,6 +524,8 @@ def main() -> int:
                    "streams": N_STREAMS, "draws_per_stream": DRAWS, "p": P, "output": "float64",
                    "lanes_per_stream": lanes},
         "bit_exact": bit_exact,
+        "init_ms": round(init_ms, 4),
+        "device": device_info(torch, dev),
         "roofline": roofline,
         "roofline_alu": roofline_alu,
         "valu_issue": valu_issue,
