@@ -9,9 +9,10 @@ output arena on the device, it is assigned the window
 are therefore fixed by the arrival order alone -- the same whether it runs
 alone or in a mix, and whatever batch it lands in.
 
-Continuous batching: whenever one of `slots` HIP streams is idle, all
-admitted-but-not-launched requests form one batch (a Plan on that slot,
-re-planned in place) and are launched on it; requests that arrive while
+Continuous batching: whenever one of `slots` HIP streams is idle, the
+admitted-but-not-launched requests, up to `batch_values` values, form one
+batch (a Plan on that slot, re-planned in place) and are launched on it; the
+cap keeps a next batch ready behind a running one.  Requests that arrive while
 other batches run are admitted as arena space and slots free up, and the
 batches on different slots overlap on the device.  Completion is observed
 with HIP events; latency is arrival -> completion of the request's batch,
@@ -98,11 +99,16 @@ class Server:
     """Request loop over `pool` streams (seed ids 0..pool-1) at luxury p."""
 
     def __init__(self, pool: int = 1_000_000, p: int = 2048, arena_values: int = 1 << 31,
-                 slots: int = 3, lanes: int = 64, seg_blocks: int = 8192, device="cuda"):
+                 slots: int = 3, lanes: int = 64, seg_blocks: int = 8192, device="cuda",
+                 batch_values: int | None = None):
         # lanes / seg_blocks: 64 lanes per segment of 8192 steps measured the
         # highest capacity on requests of 10^3..10^8 values (whole-wave
-        # segments write the longest contiguous runs)
+        # segments write the longest contiguous runs).  batch_values caps the
+        # values of one batch (default: an arena share per slot) so that the
+        # next batch is planned and queued while one runs, instead of waiting
+        # for a full arena to drain; a larger single request still goes alone.
         self.device = torch.device(device)
+        self.batch_values = batch_values if batch_values else max(1, arena_values // slots)
         self.p = p
         self.pool = pool
         self.states = new_states(pool, device=self.device)
@@ -186,6 +192,8 @@ class Server:
                     r = waiting[0]
                     c = int(count[r])
                     if arena.used + need + c > self.arena_values:
+                        break
+                    if ids and need + c > self.batch_values:
                         break
                     ids.append(r)
                     need += c
