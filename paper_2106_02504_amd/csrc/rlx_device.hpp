@@ -12,7 +12,8 @@ namespace rlx {
 // Tables of one luxury level p (device memory owned by the library):
 //   T[i][j] = A_p^(j 16^i) mod m, i < 40, j < 16 (18 words each): 4-bit
 //             windows of a 160-bit exponent; rows 0..15 serve skips of
-//             k < 2^64 steps, rows 24..39 serve seeds (exponent 2^96 id).
+//             k < 2^64 steps, rows 24..39 seeds (exponent 2^96 id).  The
+//             device-side engine uses T; the kernels use W below.
 //   C[g][j] = A_p^(2^g) 2^(o_j) mod m, g < 64, j < 21 (o_j = limb_offset(j)): the folded
 //             multiplier of a step by 2^g generator steps (see step()).
 //   W[i][j] = A_p^(j 256^i) mod m, i < 8, and W[8 + i][j] = A_p^(2^96 j 256^i)

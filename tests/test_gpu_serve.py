@@ -60,3 +60,26 @@ def test_serve_results_equal_alone(slots, arena):
         exp = O.window(x0, p, int(start[k]), int(count[k]))
         assert (outs[k] * 2.0 ** 48).astype(np.int64).tolist() == exp
     srv.close()
+
+
+@pytest.mark.parametrize("batch_values", (1, 5000, 1 << 30))
+def test_serve_batch_cap_does_not_change_values(batch_values):
+    # the cap on a batch's values only changes how requests are grouped:
+    # with one request per batch (cap 1), small batches, or no cap, every
+    # request still gets its window of its stream
+    rng = np.random.default_rng(7)
+    n, p, pool = 120, 404, 16
+    arrival = np.zeros(n)                      # all at once: admission order = index
+    stream_id = rng.integers(0, pool, size=n).astype(np.uint64)
+    count = np.floor(10.0 ** (1 + 3 * rng.random(n))).astype(np.uint64)
+    srv = Server(pool=pool, p=p, arena_values=1 << 20, slots=3, lanes=16, seg_blocks=32,
+                 batch_values=batch_values)
+    stats, outs = srv.run(arrival, stream_id, count, keep_outputs=True)
+    start = fifo_starts(stream_id, count, arrival)
+    assert np.array_equal(stats.extra["starts"], start)
+    if batch_values == 1:
+        assert stats.batches == n
+    for k in random.Random(batch_values).sample(range(n), 10):
+        exp = O.window(O.seed(int(stream_id[k]), p), p, int(start[k]), int(count[k]))
+        assert (outs[k] * 2.0 ** 48).astype(np.int64).tolist() == exp, k
+    srv.close()
