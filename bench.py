@@ -107,10 +107,16 @@ def cpu_baseline(n_streams: int, workers: int):
 # ---------------------------------------------------------------------------
 
 def sources_sha() -> str:
+    """Hash of the generate kernel's sources with comments and blank space
+    removed, so that only code changes invalidate the counter summary."""
+    import re
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, rel), encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
