@@ -316,9 +316,9 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (--gpus {args.gpus} requested); "
-              "the streams are independent and the multi-GPU sharding is described in DESIGN.md",
-              file=sys.stderr)
+        print(f"bench.py measures one GPU (--gpus {args.gpus} requested): the streams are independent, "
+              "so several GPUs would each run this workload on their own range of stream ids with no "
+              "exchange; run it with --gpus 1", file=sys.stderr)
         return 2
 
     import workloads
