@@ -8,6 +8,8 @@ exponentiation, then draw 4096 float64 uniforms per stream (2^28 doubles,
 doubles/s over whole steps.
 
 Other legs (reported beside the headline in the same JSON line):
+  ceilings   a plain 2 GiB device fill and a 1 GiB copy: the write and copy
+             rates this GPU reaches, beside the published 8 TB/s
   u64        the same step writing the 48-bit integers instead of doubles
   f32        the same streams writing float32, one RANLUX number each
              (8192 per stream: the same 2 GiB), checked against the doubles
@@ -303,7 +305,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=8192)
-    ap.add_argument("--legs", default="u64,normal,f32,lcg52,single,skip,engine,batch,serve",
+    ap.add_argument("--legs", default="ceilings,u64,normal,f32,lcg52,single,skip,engine,batch,serve",
                     help="extra legs to time (comma list or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-lanes", type=int, default=64, help="lanes per segment of the server's plans")
@@ -416,6 +418,18 @@ def main() -> int:
                               "measured kernel time; counts executed work, not algorithmic work"}
 
     legs = {}
+    if "ceilings" in wanted:
+        # what plain device fills and copies reach on this GPU: the achievable
+        # side of the published 8 TB/s (the generate kernel writes 2 GiB)
+        buf = torch.empty(1 << 28, dtype=torch.float64, device=dev)      # 2 GiB
+        half = buf[: 1 << 27]
+        other = buf[1 << 27:]
+        dt_fill = timed(lambda: buf.fill_(0.5), stream, 50, 20, torch)
+        dt_copy = timed(lambda: other.copy_(half), stream, 50, 20, torch)
+        fill_gbs = (1 << 31) / dt_fill / 1e9
+        legs["ceilings"] = {"fill_2GiB_gbs": fill_gbs, "copy_1GiB_read_plus_write_gbs": (1 << 31) / dt_copy / 1e9,
+                            "generate_fraction_of_fill": bytes_per_launch / (gen_ms * 1e-3) / 1e9 / fill_gbs}
+        del buf, half, other
     if "u64" in wanted:
         outu = torch.empty((N_STREAMS, DRAWS), dtype=torch.int64, device=dev)
 
