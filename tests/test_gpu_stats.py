@@ -1,7 +1,7 @@
 """Statistical smoke checks of the GPU output (not pins: the values are
 pinned bit for bit against the oracle elsewhere; these only catch gross
 damage such as repeated or zeroed blocks in a large launch).  The paper's
-quality claim rests on TestU01 BigCrush (section 3), which is not run
+quality claim rests on TestU01 BigCrush (section 2.5), which is not run
 here."""
 import numpy as np
 import pytest
