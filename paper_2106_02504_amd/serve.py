@@ -136,10 +136,14 @@ class Server:
         for pl in self.plans:
             pl.close()
 
-    def run(self, arrival_s, stream_id, count, keep_outputs: bool = False, max_batch: int = 4096):
+    def run(self, arrival_s, stream_id, count, keep_outputs: bool = False, max_batch: int = 4096,
+            on_complete=None):
         """Serve the requests (arrival times in seconds from now, stream ids,
         counts), in real time.  Returns ServeStats (and, with keep_outputs,
-        a list of host arrays holding each request's values)."""
+        a list of host arrays holding each request's values).  on_complete,
+        if given, is called as on_complete(request index, device view of its
+        values) when its batch has finished, before the arena space is
+        reused (the view is only valid during the call)."""
         arrival_s = np.asarray(arrival_s, dtype=np.float64)
         stream_id = np.asarray(stream_id, dtype=np.uint64)
         count = np.asarray(count, dtype=np.uint64)
@@ -181,6 +185,12 @@ class Server:
                         for r in b.ids:
                             c = int(count[r])
                             outputs[r] = host[offs:offs + c].copy()
+                            offs += c
+                    if on_complete is not None:
+                        offs = b.offset
+                        for r in b.ids:
+                            c = int(count[r])
+                            on_complete(int(r), self.arena[offs:offs + c])
                             offs += c
                     arena.release(b.offset, b.length)
                     free_slots.append(b.slot)

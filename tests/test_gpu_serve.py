@@ -83,3 +83,44 @@ def test_serve_batch_cap_does_not_change_values(batch_values):
         exp = O.window(O.seed(int(stream_id[k]), p), p, int(start[k]), int(count[k]))
         assert (outs[k] * 2.0 ** 48).astype(np.int64).tolist() == exp, k
     srv.close()
+
+
+def test_serve_full_size_sampled():
+    """The serving workload at its real size: a pool of 10^6 streams at
+    p = 2048, request sizes floor(10^(3 + 5 U)) (up to 10^8 values), Poisson
+    arrivals; 150 requests.  Requests of at most 10^5 values are checked
+    whole against the oracle, larger ones on their first, last and two
+    random windows of 512 values; every request's start is its stream's
+    cursor in arrival order."""
+    import workloads
+    reqs = workloads.serve_requests(150, 20000.0, seed=11)
+    arrival = np.array([r.arrival_s for r in reqs])
+    stream_id = np.array([r.stream_id for r in reqs], dtype=np.uint64)
+    count = np.array([r.count for r in reqs], dtype=np.uint64)
+    p = 2048
+    srv = Server(pool=workloads.SERVE["pool"], p=p, arena_values=1 << 30, slots=3, lanes=64, seg_blocks=8192)
+    rng = random.Random(12)
+    got = {}
+
+    def check(r, view):
+        c = int(count[r])
+        if c <= 100_000:
+            got[r] = [(0, view.cpu().numpy())]
+        else:
+            offs = [0, c - 512, rng.randrange(c - 512), rng.randrange(c - 512)]
+            got[r] = [(o, view[o:o + 512].cpu().numpy()) for o in offs]
+
+    stats = srv.run(arrival, stream_id, count, on_complete=check)
+    start = fifo_starts(stream_id, count, arrival)
+    assert np.array_equal(stats.extra["starts"], start)
+    assert sorted(got) == list(range(len(reqs)))
+    assert int(count.max()) > 10 ** 7                     # the large end of the size range is present
+    checked = 0
+    for r in range(len(reqs)):
+        x0 = O.seed(int(stream_id[r]), p)
+        for o, vals in got[r]:
+            exp = O.window(x0, p, int(start[r]) + o, len(vals))
+            assert (vals * 2.0 ** 48).astype(np.int64).tolist() == exp, (r, o)
+            checked += len(vals)
+    assert checked > 10 ** 5
+    srv.close()
