@@ -168,8 +168,8 @@ __device__ __forceinline__ uint32_t number_f32_bits(uint32_t v) {
 // Both output values of the field pair held in words (w0, w1, w2).  For
 // normals, Box-Muller on the pair: r = sqrt(-2 ln(1 - u1)) with u1 the even
 // field's double, and the even and odd positions get r cos(2 pi u2) and
-// r sin(2 pi u2) = r cos(2 pi u2 - pi / 2); 1 - u1 is in (0, 1] and
-// 2 u2 - 1/2 is exact.  For float32 each position holds its two RANLUX
+// r sin(2 pi u2), both from one sincospi (one range reduction); 1 - u1 is in
+// (0, 1] and 2 u2 is exact.  For float32 each position holds its two RANLUX
 // numbers (bits 0..23 and 24..47 of the field), the older one in the low
 // 32 bits, i.e. first in memory.
 template <Out K>
@@ -192,8 +192,10 @@ __device__ __forceinline__ void pair_values(uint32_t w0, uint32_t w1, uint32_t w
       b = f64_bits(u2);
     } else {
       const double r = sqrt(-2.0 * log1p(-u1));
-      a = f64_bits(r * cospi(2.0 * u2));
-      b = f64_bits(r * cospi(2.0 * u2 - 0.5));
+      double sn, cs;
+      sincospi(2.0 * u2, &sn, &cs);
+      a = f64_bits(r * cs);
+      b = f64_bits(r * sn);
     }
   }
 }
