@@ -182,7 +182,11 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
     req = rlx.requests_array([r.stream_id for r in reqs], 0, [r.count for r in reqs], [r.p for r in reqs])
     total = int(req["count"].sum())
     out = torch.empty(total, dtype=torch.float64, device=dev)
-    tuned = autotune.tune(req, st, out)
+    if args.batch_config:
+        g, sb = (int(v) for v in args.batch_config.split(":"))
+        tuned = {"lanes": g, "seg_blocks": sb, "cached": None, "fixed": True}
+    else:
+        tuned = autotune.tune(req, st, out)
     plan = rlx.Plan(req, lanes=tuned["lanes"], seg_blocks=tuned["seg_blocks"], device=dev)
     reps = max(5, args.steps // 2)
     ms = autotune.time_plan(plan, st, out, reps)
@@ -313,6 +317,8 @@ def main() -> int:
     ap.add_argument("--engine-draws", type=int, default=10 ** 6,
                     help="draws per thread in the device-engine leg (the paper's 10^6)")
     ap.add_argument("--lanes", type=int, default=0, help="force lanes per stream (0 = library's pick)")
+    ap.add_argument("--batch-config", default="",
+                    help="LANES:SEG_BLOCKS for the batch leg instead of autotuning (e.g. 32:4096)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration for rocprofv3 --pmc)")
     args = ap.parse_args()
