@@ -233,3 +233,24 @@ def test_batch_workload_sampled():
                 assert got == exp, (k, w)
     assert bool(((out >= 0) & (out < 1)).all())
     plan.close()
+
+
+def test_batch_offsets_beyond_2pow32():
+    # requests written past element 2^32 of a 34 GB output, one of them
+    # across the index 2^32 itself: offsets are 64-bit end to end
+    p = 794
+    st = make_records([(3, p), (4, p)])
+    base = 1 << 32
+    req = rlx.requests_array([0, 1, 0], [0, 123456, 5000], [1000, 777, 50000], p,
+                             out_offset=[base - 500, base + 1000, 7])
+    out = torch.full((base + 2000,), -1.0, dtype=torch.float64, device=DEV)
+    plan = rlx.Plan(req, lanes=16, seg_blocks=64)
+    plan.generate_f64(st, out)
+    torch.cuda.synchronize()
+    for (s, start, c, o) in ((0, 0, 1000, base - 500), (1, 123456, 777, base + 1000), (0, 5000, 50000, 7)):
+        got = (out[o:o + c] * 2.0 ** 48).to(torch.int64).cpu().numpy().tolist()
+        assert got == O.window(O.seed(3 + s, p), p, start, c), (s, o)
+    assert float(out[base + 500]) == -1.0 and float(out[6]) == -1.0
+    plan.close()
+    del out
+    torch.cuda.empty_cache()

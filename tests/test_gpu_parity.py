@@ -391,3 +391,32 @@ def test_lanes_short_counts_and_general_path(G, lanes_reset):
         assert a.cpu().numpy().tolist() == exp, count
         assert torch.equal(a, b) and torch.equal(st_a, st_b)
         assert tensor_to_records(st_a) == fin
+
+
+def test_output_beyond_2pow32_elements():
+    """Two records x (2^31 + 5) doubles: row 1 starts past element 2^31 and
+    ends past 2^32 (34 GB of output), so every output offset needs 64 bits.
+    Windows at the start, around the 32-bit boundaries and at the end of
+    each row are compared with the oracle, and the records after the call."""
+    p = 2048
+    count = (1 << 31) + 5
+    st = rlx.new_states(2)
+    rlx.init_streams(st, p, id0=40)
+    out = rlx.generate_f64(st, count, p)
+    torch.cuda.synchronize()
+    flat = out.view(-1)
+    for r in range(2):
+        x0 = O.seed(40 + r, p)
+        for j in (0, (1 << 31) - 30, count - 40):    # windows inside the row, one across index 2^31
+            k = r * count + j
+            got = (flat[k:k + 35] * 2.0 ** 48).to(torch.int64).cpu().numpy().tolist()
+            assert got == O.window(x0, p, j, 35), (r, j)
+    # the element at global index 2^32 and its neighbours (row 1)
+    k = 1 << 32
+    got = (flat[k - 3:k + 3] * 2.0 ** 48).to(torch.int64).cpu().numpy().tolist()
+    assert got == O.window(O.seed(41, p), p, k - 3 - count, 6)
+    recs = tensor_to_records(st)
+    for r in range(2):
+        assert recs[r] == O.state_at(O.seed(40 + r, p), p, count) + (p,)
+    del out, flat
+    torch.cuda.empty_cache()
