@@ -95,3 +95,39 @@ def test_arena_first_fit():
     a.release(y, 40)
     a.release(0, 30)
     assert a.free == [(0, 100)] and a.used == 0
+
+
+# --- property test: any request set, any launch shape ---------------------------
+
+from hypothesis import given, settings, strategies as st_  # noqa: E402
+
+
+@settings(max_examples=60, deadline=None)
+@given(data=st_.data(),
+       lanes=st_.sampled_from([1, 2, 4, 8, 16, 32, 64]),
+       seg=st_.integers(min_value=1, max_value=300))
+def test_planner_tiles_any_request_set(data, lanes, seg):
+    n = data.draw(st_.integers(min_value=0, max_value=25))
+    counts = data.draw(st_.lists(st_.integers(min_value=0, max_value=4000), min_size=n, max_size=n))
+    starts = data.draw(st_.lists(st_.integers(min_value=0, max_value=(1 << 40)), min_size=n, max_size=n))
+    ps = data.draw(st_.lists(st_.sampled_from([24, 25, 218, 404, 2048]), min_size=n, max_size=n))
+    gaps = data.draw(st_.lists(st_.integers(min_value=0, max_value=50), min_size=n, max_size=n))
+    offs, o = [], 0
+    for c, g in zip(counts, gaps):          # disjoint output windows with gaps
+        o += g
+        offs.append(o)
+        o += c
+    req = rlx.requests_array(list(range(n)), starts, counts, ps, out_offset=offs)
+    if n == 0:
+        req = np.zeros(0, dtype=rlx.REQUEST_DTYPE)
+    segs, n_items = check_plan(req, lanes, seg)
+    # one luxury level per item: segments of an item are consecutive rows
+    per_item = 64 // lanes
+    slots = [int(r[5]) >> 32 for r in segs]
+    assert len(segs) <= n_items * per_item
+    for k, q in enumerate(req):
+        if q["count"] == 0:
+            continue
+        mine = [r for r in segs if int(r[0]) == k]
+        assert min(int(r[1]) for r in mine) == int(q["start"]) // 12
+    assert len(set(slots)) <= len(set(ps)) if n else True
