@@ -167,7 +167,7 @@ def timed(fn, stream, steps, warmup, torch):
 
 def batch_leg(rlx, torch, np, dev, reqs, checks, args):
     """8192 requests (own stream each, p uniform over 5 levels, log-uniform
-    counts in [1, 2^20]) in one persistent launch; lanes per segment and
+    counts in [1, 2^20]) in one fused launch; lanes per segment and
     segment length from the autotuner; also replayed from a HIP graph."""
     from paper_2106_02504_amd import autotune
     n = len(reqs)
@@ -228,7 +228,7 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
             "requests": n, "values": total, "segments": info["segments"], "items": info["items"],
             "bit_exact_sample": exact,
             "workload": "8192 requests, own stream each (id r), p uniform over {24,218,404,794,2048}, "
-                        "counts floor(2^(20U)) in [1, 2^20], one persistent launch"}
+                        "counts floor(2^(20U)) in [1, 2^20], one fused launch"}
 
 
 def serve_leg(rlx, torch, np, dev, plain_rate, args):

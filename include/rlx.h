@@ -250,7 +250,7 @@ int rlx_set_lanes_per_stream(uint32_t lanes);
 uint32_t rlx_lanes_per_stream(uint64_t n, uint64_t count);
 
 /* ---- batched generation ---------------------------------------------------
- * Many requests, each a window of one stream, in ONE persistent launch that
+ * Many requests, each a window of one stream, in ONE launch that
  * fuses skip-ahead, generation and conversion.  A request reads its stream
  * record without modifying it, so several requests may read the same record
  * (e.g. consecutive windows of one stream) and their results are exactly the
@@ -298,8 +298,8 @@ int rlx_plan_update(rlx_plan *plan, const rlx_request *reqs, uint64_t n, void *s
 int rlx_plan_info(const rlx_plan *plan, uint64_t *segments, uint64_t *items,
                   uint64_t *total_values);
 
-/* Run the plan: one counter-reset kernel and one persistent kernel on
- * `stream` (no allocation, no synchronisation, no memset: capturable).
+/* Run the plan: one kernel on `stream`, one wave per work item (no
+ * allocation, no synchronisation, no memset: capturable).
  * The launch reads the work list, its length and the luxury tables from the
  * plan's device memory, so a captured launch runs whatever requests the plan
  * holds when it is replayed.  `states` are read only.  out must hold every

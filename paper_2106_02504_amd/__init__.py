@@ -360,7 +360,7 @@ def requests_array(state, start, count, p, out_offset=None) -> "_np.ndarray":
 
 
 class Plan:
-    """A batch of requests planned for the persistent kernel (rlx_plan_*).
+    """A batch of requests planned for the batched kernel (rlx_plan_*).
 
     `requests` is a host array of REQUEST_DTYPE.  lanes: lanes per segment
     (power of two <= 64); seg_blocks: maximum generator steps per segment.
@@ -445,7 +445,7 @@ class Plan:
 def batch(states: torch.Tensor, requests, out: torch.Tensor | None = None, lanes: int = 32,
           seg_blocks: int = 4096, dtype: torch.dtype = torch.float64) -> torch.Tensor:
     """One-shot batched generation: plan `requests` (REQUEST_DTYPE, e.g. from
-    requests_array), run the persistent launch and free the plan (which
+    requests_array), run the batched launch and free the plan (which
     synchronises the device).  dtype float64, int64 (the 48-bit values) or
     float32 (two floats per position).  `out` is allocated to the requests'
     extent when None.  For repeated batches keep a Plan, whose launches can be

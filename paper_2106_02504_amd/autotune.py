@@ -1,6 +1,6 @@
 """Autotuner for batched generation: picks the lanes per segment and the
 segment length (generator steps per segment, i.e. draws per lane = 12 *
-seg_blocks / lanes) of a Plan by timing the persistent launch on the GPU.
+seg_blocks / lanes) of a Plan by timing the batched launch on the GPU.
 
 Every candidate produces bit-identical values (the tests check this), so the
 choice only affects speed.  Results are cached in a JSON file keyed by the
@@ -60,7 +60,7 @@ def _store(doc: dict) -> None:
 
 
 def time_plan(plan: Plan, states: torch.Tensor, out: torch.Tensor, reps: int = 5) -> float:
-    """Average milliseconds of one persistent launch (HIP events on the
+    """Average milliseconds of one batched launch (HIP events on the
     current stream)."""
     gen = plan.generate_f64 if out.dtype == torch.float64 else plan.generate_u64
     gen(states, out)

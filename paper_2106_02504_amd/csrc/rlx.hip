@@ -7,7 +7,7 @@
 //   k_generate<U64|F64|NORMAL|F32, trace, LGS> draw values (sections 2.1-2.3)
 //   k_generate_lcg52<LGS>                  legacy raw-LCG doubles (section 2.3)
 //   k_test_*                               generic arithmetic for tests
-// The batched persistent kernel and its planner are in rlx_batch.hip.
+// The batched kernel and its planner are in rlx_batch.hip.
 #include <hip/hip_runtime.h>
 
 #include <atomic>

@@ -1,19 +1,22 @@
-// rlx_batch.hip -- batched generation: planner and persistent kernel.
+// rlx_batch.hip -- batched generation: planner and one fused kernel.
 //
 // A batch is a list of requests, each a window [start, start + count) of one
 // stream (values counted from field 0 of the record's current step).  The
 // planner (host) cuts every request into segments of at most `seg_blocks`
 // generator steps and groups segments of the same luxury level into work
-// items of 64 lanes (64 / G segments of G lanes each).  One persistent
-// kernel then pops items from a device counter; inside an item every segment
-// is run by G lanes exactly as the plain kernel runs a record: lane l starts
-// at the segment's block l (skip by folded steps of A^(2^g), section 2.4),
-// then takes every G-th block with the multiplier A^G, converts (section
-// 2.3) and stores through LDS.  Records are only read.
+// items of 64 lanes (64 / G segments of G lanes each).  One kernel then
+// runs one wave per item; inside an item every segment is run by G lanes
+// exactly as the plain kernel runs a record: lane l starts at the segment's
+// block l (skip by 8-bit windows, section 2.4), then takes every G-th block
+// with the multiplier A^G, converts (section 2.3) and stores through LDS.
+// Records are only read.
 //
 // Segments are sorted by length (longest first) inside a level and items by
-// cost, so waves that pop late get short items (longest-processing-time
-// order); long requests are cut so that no item dominates the launch.
+// cost, and the hardware dispatches waves in item order, so late waves get
+// short items (longest-processing-time order); long requests are cut so
+// that no item dominates the launch.  One wave per item, rather than
+// persistent waves popping items from a counter, keeps the kernel's
+// registers at the plain kernel's level (5 waves per SIMD instead of 4).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -60,17 +63,13 @@ static_assert(sizeof(Item) == 16, "item descriptor layout");
 // change between updates lives here (not in kernel arguments), so a launch
 // captured in a HIP graph replays whatever the plan holds at replay time.
 struct Header {
-  uint32_t counter;  // next work item (reset before every launch)
+  uint32_t reserved;
   uint32_t n_items;
   uint32_t pad[2];
   const uint32_t* C[MAX_LEVELS];  // folded multipliers A^(2^g) of each level
   const uint32_t* W[MAX_LEVELS];  // 8-bit window tables A^(j 256^i) of each level
   uint32_t p[MAX_LEVELS];
 };
-
-__global__ void k_reset(Header* __restrict__ hdr) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) hdr->counter = 0;
-}
 
 template <Out K, int LGS>
 __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ st,
@@ -84,11 +83,11 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ s
   const uint32_t team = lane >> LGS;
   const uint32_t l = lane & (G - 1);
   const uint32_t n_items = __builtin_amdgcn_readfirstlane(hdr->n_items);
-  for (;;) {
-    uint32_t it = 0;
-    if (lane == 0) it = atomicAdd(&hdr->counter, 1u);
-    it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
-    if (it >= n_items) break;
+  {
+    // wave w of the grid runs item w; the grid covers the plan's capacity,
+    // so waves past the current item count exit at once
+    const uint32_t it = __builtin_amdgcn_readfirstlane(blockIdx.x * (BLOCK / WAVE) + tid_blk / WAVE);
+    if (it >= n_items) return;
     const Item item = items[it];
     const uint32_t slot = __builtin_amdgcn_readfirstlane(item.slot);
     const uint32_t* __restrict__ ctabs = hdr->C[slot];
@@ -321,11 +320,11 @@ int plan_launch(rlx_plan* plan, const rlx_state* states, void* out, void* stream
   uint32_t* err;
   int rc = error_word(s, &err);
   if (rc) return rc;
-  // The grid depends only on the plan's capacity, so a captured launch stays
-  // valid after updates: enough waves to fill the chip (or one per item of a
-  // full plan); waves that find the queue empty exit.
-  const uint64_t blocks = std::min<uint64_t>((plan->cap + 3) / 4, 256ull * 8);
-  k_reset<<<1, 64, 0, s>>>(plan->d_hdr);
+  // One wave per item of a full plan (items never outnumber the segment
+  // capacity).  The grid depends only on the capacity, so a captured launch
+  // stays valid after updates; waves past the current item count exit.
+  const uint64_t blocks = (plan->cap + (BLOCK / WAVE) - 1) / (BLOCK / WAVE);
+  if (blocks == 0 || blocks > 0x7FFFFFFFull) return RLX_EINVAL;
   uint64_t* o = reinterpret_cast<uint64_t*>(out);
 #define RLX_BATCH(L)                                                                                      \
   case L:                                                                                                 \

@@ -1,4 +1,4 @@
-"""Batched generation (persistent kernel + planner) against the oracle and
+"""Batched generation (fused kernel + planner) against the oracle and
 against the plain kernel, bit for bit.
 
 A request is a window [start, start + count) of one stream, counted from
@@ -128,7 +128,7 @@ def test_plan_update_and_graph_replays():
     out = torch.zeros(cap_vals, dtype=torch.int64, device=DEV)
     req0 = new_requests(0)
     plan = rlx.Plan(req0, lanes=8, seg_blocks=16, capacity_segments=4096)
-    # capture the launch (reset kernel + persistent kernel) in a graph
+    # capture the launch in a graph
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
