@@ -442,7 +442,7 @@ class Plan:
             pass
 
 
-def batch(states: torch.Tensor, requests, out: torch.Tensor | None = None, lanes: int = 32,
+def batch(states: torch.Tensor, requests, out: torch.Tensor | None = None, lanes: int = 64,
           seg_blocks: int = 4096, dtype: torch.dtype = torch.float64) -> torch.Tensor:
     """One-shot batched generation: plan `requests` (REQUEST_DTYPE, e.g. from
     requests_array), run the batched launch and free the plan (which
