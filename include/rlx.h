@@ -97,9 +97,10 @@ const char *rlx_version(void);
 /* Build (if needed) the constant tables of luxury level p on the current
  * device, on `stream`, and wait for them.  p >= 24.  Tables: A_p folded for
  * the generator step; A_p^(j 16^i) for i < 40, j < 16 (4-bit windows, the
- * device-side engine's); and A_p^(j 256^i) and A_p^(2^96 j 256^i) for i < 8,
- * j < 256 (8-bit windows, used by the library's seeding, skipping and lane
- * start-up; section 2.4: exponentiation by windows). */
+ * device-side engine's); and A_p^(j 65536^i) and A_p^(2^96 j 65536^i) for
+ * i < 4, j < 65536 (16-bit windows, 37.7 MB per level, used by the library's
+ * seeding, skipping and lane start-up; section 2.4: exponentiation by
+ * windows). */
 int rlx_prepare(uint32_t p, void *stream);
 
 /* Layout of the device tables of one luxury level p (section 2.4; words are

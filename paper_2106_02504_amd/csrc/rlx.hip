@@ -1,7 +1,7 @@
 // rlx.hip -- RANLUX++ kernels for gfx950 and the C ABI of librlx.so.
 //
 // Kernels (one lane per stream record unless noted):
-//   k_tab_base / k_tab_fill / k_tab_fold / k_tab_w8   per-luxury-level tables
+//   k_tab_base / k_tab_fill / k_tab_fold / k_tab_win   per-luxury-level tables
 //   k_init                                 seeding        (section 2.4)
 //   k_skip                                 skip-ahead     (section 2.4)
 //   k_generate<U64|F64|NORMAL|F32, trace, LGS> draw values (sections 2.1-2.3)
@@ -67,19 +67,22 @@ __global__ __launch_bounds__(64) void k_tab_fill(uint32_t* __restrict__ T) {
   store_words(T + ((size_t)i * TAB_COLS + j) * NW, r);
 }
 
-// W[i][j] = T[r][j mod 16] T[r + 1][j / 16] with r = 2i for the skip rows
-// (i < 8) and r = 24 + 2 (i - 8) for the seed rows: A_p^(j 256^i) from two
-// hexadecimal windows.  One lane per entry.
-__global__ __launch_bounds__(64) void k_tab_w8(const uint32_t* __restrict__ T, uint32_t* __restrict__ W) {
+// W[i][j] = prod_q T[r + q][nibble q of j], q < 4, with r = 4i for the skip
+// rows (i < 4) and r = 24 + 4 (i - 4) for the seed rows: A_p^(j 65536^i)
+// from four hexadecimal windows.  One lane per entry.
+__global__ __launch_bounds__(64) void k_tab_win(const uint32_t* __restrict__ T, uint32_t* __restrict__ W) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= W8_ROWS * W8_COLS) return;
-  const int i = t / W8_COLS;
-  const uint32_t j = (uint32_t)(t % W8_COLS);
-  const int r = i < W8_SEED_ROW0 ? 2 * i : SEED_ROW0 + 2 * (i - W8_SEED_ROW0);
-  uint32_t a[NW], b[NW], y[NW];
-  load_words(T + ((size_t)r * TAB_COLS + (j & 15u)) * NW, a);
-  load_words(T + ((size_t)(r + 1) * TAB_COLS + (j >> 4)) * NW, b);
-  mulmod_generic(a, b, y);
+  if (t >= WIN_ROWS * WIN_COLS) return;
+  const int i = t / WIN_COLS;
+  const uint32_t j = (uint32_t)(t % WIN_COLS);
+  const int r = i < WIN_SEED_ROW0 ? 4 * i : SEED_ROW0 + 4 * (i - WIN_SEED_ROW0);
+  uint32_t y[NW], a[NW];
+  load_words(T + ((size_t)r * TAB_COLS + (j & 15u)) * NW, y);
+#pragma unroll 1
+  for (int q = 1; q < 4; ++q) {
+    load_words(T + ((size_t)(r + q) * TAB_COLS + ((j >> (4 * q)) & 15u)) * NW, a);
+    mulmod_inplace(y, a);
+  }
   store_words(W + (size_t)t * NW, y);
 }
 
@@ -103,7 +106,8 @@ __global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T,
 // seeding and skipping (section 2.4)
 
 // X = A_p^(2^96 id) from 1: the product of the seed windows of the non-zero
-// bytes of id (the first one copied, not multiplied).
+// 16-bit digits of id (the first one copied, not multiplied: ids < 2^16 are
+// a table copy).
 __global__ __launch_bounds__(BLOCK) void k_init(rlx_state* __restrict__ st, uint64_t n,
                                                 const uint64_t* __restrict__ ids, uint64_t id0,
                                                 uint32_t p, const uint32_t* __restrict__ W) {
@@ -113,10 +117,10 @@ __global__ __launch_bounds__(BLOCK) void k_init(rlx_state* __restrict__ st, uint
   uint32_t x[NW];
   set_one(x);
   bool first = true;
-  for (int b = 0; b < 8 && (id >> (8 * b)) != 0; ++b) {
-    const uint32_t v = (uint32_t)(id >> (8 * b)) & 255u;
+  for (int b = 0; b < 4 && (id >> (WIN_BITS * b)) != 0; ++b) {
+    const uint32_t v = (uint32_t)(id >> (WIN_BITS * b)) & (WIN_COLS - 1u);
     if (v == 0) continue;
-    const uint32_t* e = W + ((size_t)(W8_SEED_ROW0 + b) * W8_COLS + v) * NW;
+    const uint32_t* e = W + ((size_t)(WIN_SEED_ROW0 + b) * WIN_COLS + v) * NW;
     uint32_t y[NW];
     load_words(e, y);
     if (first) {
@@ -521,7 +525,7 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
     (void)hipFree(t.T);
     return RLX_ENOMEM;
   }
-  if (hipMalloc(&t.W, W8_WORDS * sizeof(uint32_t)) != hipSuccess) {
+  if (hipMalloc(&t.W, WIN_WORDS * sizeof(uint32_t)) != hipSuccess) {
     (void)hipFree(t.T);
     (void)hipFree(t.C);
     return RLX_ENOMEM;
@@ -530,7 +534,7 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
   const int fill = TAB_ROWS * (TAB_COLS - 2);
   k_tab_fill<<<(fill + 63) / 64, 64, 0, s>>>(t.T);
   k_tab_fold<<<FOLD_G, 64, 0, s>>>(t.T, t.C);
-  k_tab_w8<<<(W8_ROWS * W8_COLS + 63) / 64, 64, 0, s>>>(t.T, t.W);
+  k_tab_win<<<(WIN_ROWS * WIN_COLS + 63) / 64, 64, 0, s>>>(t.T, t.W);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     (void)hipFree(t.T);
     (void)hipFree(t.C);
@@ -555,8 +559,8 @@ std::atomic<uint32_t> g_lanes_override{0};
 // the launch stays within sixteen waves per SIMD (2^20 lanes on 256 CUs) and
 // every lane still takes at least 16 generator steps -- or, while the launch
 // has fewer lanes than one wave per SIMD (2^16), at least one step.  A lane
-// pays one windowed multiplication per non-zero byte of its index at
-// start-up, so G trades start-up work against parallelism and against the
+// pays one windowed multiplication per non-zero 16-bit digit of its index
+// at start-up, so G trades start-up work against parallelism and against the
 // length of the contiguous runs each store instruction writes (16 G bytes
 // per record).  On the many-streams shape G = 16 measured fastest; a single
 // stream of 2^20 values ran in 32 us at G = 65536 against 68 us at 4096.

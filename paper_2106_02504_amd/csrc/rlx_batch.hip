@@ -7,7 +7,7 @@
 // items of 64 lanes (64 / G segments of G lanes each).  One kernel then
 // runs one wave per item; inside an item every segment is run by G lanes
 // exactly as the plain kernel runs a record: lane l starts at the segment's
-// block l (skip by 8-bit windows, section 2.4), then takes every G-th block
+// block l (skip by 16-bit windows, section 2.4), then takes every G-th block
 // with the multiplier A^G, converts (section 2.3) and stores through LDS.
 // Records are only read.
 //
@@ -67,7 +67,7 @@ struct Header {
   uint32_t n_items;
   uint32_t pad[2];
   const uint32_t* C[MAX_LEVELS];  // folded multipliers A^(2^g) of each level
-  const uint32_t* W[MAX_LEVELS];  // 8-bit window tables A^(j 256^i) of each level
+  const uint32_t* W[MAX_LEVELS];  // 16-bit window tables A^(j 65536^i) of each level
   uint32_t p[MAX_LEVELS];
 };
 

@@ -16,11 +16,11 @@ namespace rlx {
 //             device-side engine uses T; the kernels use W below.
 //   C[g][j] = A_p^(2^g) 2^(o_j) mod m, g < 64, j < 21 (o_j = limb_offset(j)): the folded
 //             multiplier of a step by 2^g generator steps (see step()).
-//   W[i][j] = A_p^(j 256^i) mod m, i < 8, and W[8 + i][j] = A_p^(2^96 j 256^i)
-//             mod m, j < 256: 8-bit windows for skips of k < 2^64 steps and
-//             for seeds with ids < 2^64, each entry the product of two
-//             entries of T (the kernels' own table; the device-side engine
-//             of rlx_engine.h uses T).
+//   W[i][j] = A_p^(j 65536^i) mod m, i < 4, and W[4 + i][j] =
+//             A_p^(2^96 j 65536^i) mod m, j < 65536 (37.7 MB): 16-bit windows
+//             for skips of k < 2^64 steps and for seeds with ids < 2^64, each
+//             entry the product of four entries of T (the kernels' own table;
+//             the device-side engine of rlx_engine.h uses T).
 constexpr int TAB_ROWS = RLX_TAB_ROWS;
 constexpr int TAB_COLS = RLX_TAB_COLS;
 constexpr int SEED_ROW0 = RLX_SEED_ROW0;  // 2^96 = 16^24
@@ -28,10 +28,11 @@ constexpr size_t TAB_WORDS = (size_t)TAB_ROWS * TAB_COLS * NW;
 constexpr int FOLD_G = RLX_FOLD_G;
 constexpr size_t FOLD_ROW_WORDS = (size_t)NL * NW;  // one folded multiplier
 constexpr size_t FOLD_WORDS = (size_t)FOLD_G * FOLD_ROW_WORDS;
-constexpr int W8_ROWS = 16;
-constexpr int W8_COLS = 256;
-constexpr int W8_SEED_ROW0 = 8;
-constexpr size_t W8_WORDS = (size_t)W8_ROWS * W8_COLS * NW;
+constexpr int WIN_BITS = 16;
+constexpr int WIN_ROWS = 8;
+constexpr int WIN_COLS = 1 << WIN_BITS;
+constexpr int WIN_SEED_ROW0 = 4;
+constexpr size_t WIN_WORDS = (size_t)WIN_ROWS * WIN_COLS * NW;
 constexpr int BLOCK = 256;
 constexpr int FIELDS = 12;
 constexpr int WAVE = 64;
@@ -106,20 +107,20 @@ __device__ __forceinline__ void mulmod_inplace(uint32_t (&x)[NW], const uint32_t
   copy_words(x, r);
 }
 
-// X <- A^e X by 8-bit windows: one generic multiplication per non-zero
-// byte of e by the table entry A^(v 256^i) (rows 0..7 of W, section 2.4).
-// The lanes of a wave take different exponents, so the wave runs as many
-// rounds as its longest exponent has bytes, each lane multiplying when its
-// byte is non-zero; 8-bit windows halve the rounds of 4-bit ones.  Starting
-// the lanes of a record this way (e = lane index, or the segment's first
-// step plus the lane index) costs one per-lane multiplication for e < 256.
+// X <- A^e X by 16-bit windows: one generic multiplication per non-zero
+// 16-bit digit of e by the table entry A^(v 65536^i) (rows 0..3 of W,
+// section 2.4).  The lanes of a wave take different exponents, so the wave
+// runs as many rounds as its longest exponent has digits (at most 4), each
+// lane multiplying when its digit is non-zero.  Starting the lanes of a
+// record this way (e = lane index, or the segment's first step plus the
+// lane index) costs one per-lane multiplication for e < 65536.
 __device__ __forceinline__ void skip_windows(uint32_t (&x)[NW], uint64_t e, const uint32_t* __restrict__ W) {
 #pragma unroll 1
-  for (int b = 0; b < 8 && __any((e >> (8 * b)) != 0); ++b) {
-    const uint32_t v = (uint32_t)(e >> (8 * b)) & 255u;
+  for (int b = 0; b < 4 && __any((e >> (WIN_BITS * b)) != 0); ++b) {
+    const uint32_t v = (uint32_t)(e >> (WIN_BITS * b)) & (WIN_COLS - 1u);
     if (v != 0) {
       uint32_t y[NW];
-      load_words(W + ((size_t)b * W8_COLS + v) * NW, y);
+      load_words(W + ((size_t)b * WIN_COLS + v) * NW, y);
       mulmod_inplace(x, y);
     }
   }

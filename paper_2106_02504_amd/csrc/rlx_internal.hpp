@@ -14,7 +14,7 @@ namespace host {
 struct Tables {
   uint32_t* T = nullptr;  // TAB_WORDS words
   uint32_t* C = nullptr;  // FOLD_WORDS words
-  uint32_t* W = nullptr;  // W8_WORDS words
+  uint32_t* W = nullptr;  // WIN_WORDS words
 };
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
