@@ -21,8 +21,10 @@
  *   Memory     All array pointers are DEVICE pointers owned by the caller
  *              (e.g. PyTorch tensors).  The library never allocates, frees or
  *              retains caller memory.  It owns only per-(device, p) constant
- *              tables, one error word per device and the descriptors of
- *              batch plans (rlx_plan_create .. rlx_plan_destroy).
+ *              tables (about 38 MB per luxury level and device, kept until
+ *              the process exits), one error word per device and the
+ *              descriptors of batch plans (rlx_plan_create ..
+ *              rlx_plan_destroy).
  *   Streams    `stream` is a hipStream_t passed as void*; NULL is the default
  *              stream.  Work runs on the current HIP device and is enqueued
  *              asynchronously: calls return before the GPU has finished, and
