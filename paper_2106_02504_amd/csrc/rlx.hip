@@ -14,6 +14,7 @@
 #include <cstdint>
 #include <map>
 #include <mutex>
+#include <new>
 #include <utility>
 
 #include "rlx.h"
@@ -504,7 +505,12 @@ int error_word(hipStream_t s, uint32_t** out) {
     (void)hipFree(w);
     return RLX_EHIP;
   }
-  g_err[dev] = w;
+  try {
+    g_err[dev] = w;
+  } catch (const std::bad_alloc&) {
+    (void)hipFree(w);
+    return RLX_ENOMEM;
+  }
   *out = w;
   return RLX_OK;
 }
@@ -541,7 +547,14 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
     (void)hipFree(t.W);
     return RLX_EHIP;
   }
-  g_tables[key] = t;
+  try {
+    g_tables[key] = t;
+  } catch (const std::bad_alloc&) {
+    (void)hipFree(t.T);
+    (void)hipFree(t.C);
+    (void)hipFree(t.W);
+    return RLX_ENOMEM;
+  }
   *out = t;
   return RLX_OK;
 }

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstdint>
 #include <cstring>
+#include <new>
 #include <vector>
 
 #include "rlx.h"
@@ -312,9 +313,16 @@ void free_plan(rlx_plan* p) {
   delete p;
 }
 
+// The plan's tables and descriptors live on the device it was created on.
+bool on_plan_device(const rlx_plan* plan) {
+  int dev;
+  return hipGetDevice(&dev) == hipSuccess && dev == plan->device;
+}
+
 template <Out K>
 int plan_launch(rlx_plan* plan, const rlx_state* states, void* out, void* stream) {
   if (!plan) return RLX_EINVAL;
+  if (!on_plan_device(plan)) return RLX_EINVAL;
   if (!states || !out || !aligned(states, 16) || !aligned(out, 8)) return RLX_EINVAL;
   hipStream_t s = as_stream(stream);
   uint32_t* err;
@@ -344,17 +352,20 @@ int plan_launch(rlx_plan* plan, const rlx_state* states, void* out, void* stream
 extern "C" {
 
 int rlx_plan_create(rlx_plan** plan, const rlx_request* reqs, uint64_t n, uint32_t lanes, uint64_t seg_blocks,
-                    uint64_t capacity_segments, void* stream) {
+                    uint64_t capacity_segments, void* stream) try {
   if (!plan) return RLX_EINVAL;
   *plan = nullptr;
   if (n > 0 && !reqs) return RLX_EINVAL;
   if (lanes == 0 || lanes > (uint32_t)WAVE || (lanes & (lanes - 1)) != 0) return RLX_EINVAL;
   if (seg_blocks == 0 || seg_blocks > RLX_MAX_SEG_BLOCKS) return RLX_EINVAL;
+  // a plan never holds more than 2^32 - 1 segments (the planner's limit)
+  if (capacity_segments > 0xFFFFFFFFull) return RLX_EINVAL;
   const uint32_t lg = (uint32_t)__builtin_ctz(lanes);
   Planned pl;
   int rc = plan_requests(reqs, n, lg, seg_blocks, &pl);
   if (rc) return rc;
-  rlx_plan* p = new rlx_plan();
+  rlx_plan* p = new (std::nothrow) rlx_plan();
+  if (!p) return RLX_ENOMEM;
   if (hipGetDevice(&p->device) != hipSuccess) {
     free_plan(p);
     return RLX_EHIP;
@@ -384,14 +395,19 @@ int rlx_plan_create(rlx_plan** plan, const rlx_request* reqs, uint64_t n, uint32
   }
   *plan = p;
   return RLX_OK;
+} catch (const std::bad_alloc&) {
+  return RLX_ENOMEM;
 }
 
-int rlx_plan_update(rlx_plan* plan, const rlx_request* reqs, uint64_t n, void* stream) {
+int rlx_plan_update(rlx_plan* plan, const rlx_request* reqs, uint64_t n, void* stream) try {
   if (!plan || (n > 0 && !reqs)) return RLX_EINVAL;
+  if (!on_plan_device(plan)) return RLX_EINVAL;
   Planned pl;
   int rc = plan_requests(reqs, n, plan->lg, plan->seg_blocks, &pl);
   if (rc) return rc;
   return upload(plan, pl, as_stream(stream));
+} catch (const std::bad_alloc&) {
+  return RLX_ENOMEM;
 }
 
 int rlx_plan_info(const rlx_plan* plan, uint64_t* segments, uint64_t* items, uint64_t* total_values) {
@@ -416,7 +432,7 @@ int rlx_plan_generate_f32(rlx_plan* plan, const rlx_state* states, float* out, v
 
 int rlx_plan_dry_run(const rlx_request* reqs, uint64_t n, uint32_t lanes, uint64_t seg_blocks,
                      uint64_t* n_segments, uint64_t* n_items, uint64_t* total_values, uint64_t* segments,
-                     uint64_t max_segments) {
+                     uint64_t max_segments) try {
   if (n > 0 && !reqs) return RLX_EINVAL;
   if (lanes == 0 || lanes > (uint32_t)WAVE || (lanes & (lanes - 1)) != 0) return RLX_EINVAL;
   if (seg_blocks == 0 || seg_blocks > RLX_MAX_SEG_BLOCKS) return RLX_EINVAL;
@@ -442,6 +458,8 @@ int rlx_plan_dry_run(const rlx_request* reqs, uint64_t n, uint32_t lanes, uint64
     }
   }
   return RLX_OK;
+} catch (const std::bad_alloc&) {
+  return RLX_ENOMEM;
 }
 
 int rlx_plan_destroy(rlx_plan* plan) {

@@ -128,3 +128,13 @@ def test_ranlux_form_argument_checks(rlx):
     assert lib.rlx_import_ranlux(v(16), 3, v(12), v(16), None, 24, None) == 1  # packed not 8-byte aligned
     assert lib.rlx_import_ranlux(v(16), 3, v(16), v(16), None, 23, None) == 1
     assert lib.rlx_export_ranlux(None, 0, None, None, None, None) == 0
+
+
+def test_plan_capacity_limit(rlx):
+    # a capacity beyond 2^32 - 1 segments is rejected before any device work
+    lib = rlx.lib()
+    req = rlx.requests_array([0], [0], [10], 2048)
+    h = ctypes.c_void_p()
+    assert lib.rlx_plan_create(ctypes.byref(h), req.ctypes.data, 1, 8, 64, 1 << 33, None) == 1
+    assert not h.value
+    assert lib.rlx_plan_create(None, req.ctypes.data, 1, 8, 64, 0, None) == 1
