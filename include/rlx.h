@@ -283,7 +283,9 @@ typedef struct rlx_request {
 typedef struct rlx_plan rlx_plan;
 
 /* Create a plan for n host requests (capacity for later updates is sized
- * for `capacity_segments` segments; 0 = exactly what these requests need).
+ * for `capacity_segments` segments, at most 2^32 - 1; 0 = exactly what these
+ * requests need).  A plan belongs to the device current at creation: update
+ * and generate calls made with another device current return RLX_EINVAL.
  * Builds the tables of every luxury level used (synchronising `stream`
  * once per new level) and uploads the descriptors on `stream`. */
 int rlx_plan_create(rlx_plan **plan, const rlx_request *reqs, uint64_t n,
