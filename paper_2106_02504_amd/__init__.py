@@ -498,22 +498,32 @@ def constants() -> tuple[int, int]:
 
 # ---- test-only entry points ------------------------------------------------
 
+def _need_words(t: torch.Tensor, n: int | None, what: str, words: int = 9) -> int:
+    """A contiguous device int64/uint64 tensor of shape [n, words]."""
+    if (t.dtype not in (torch.int64, torch.uint64) or t.dim() != 2 or t.shape[1] != words or not t.is_cuda
+            or not t.is_contiguous() or (n is not None and t.shape[0] != n)):
+        raise ValueError(f"{what} must be a contiguous device int64 tensor of shape [n, {words}]")
+    return t.shape[0]
+
+
 def test_mulmod(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
-    n = x.shape[0]
+    n = _need_words(x, None, "x")
+    _need_words(y, n, "y")
     out = torch.empty_like(x)
     _check(lib().rlx_test_mulmod(x.data_ptr(), y.data_ptr(), out.data_ptr(), n, _stream()), "rlx_test_mulmod")
     return out
 
 
 def test_pow(base: torch.Tensor, exps: torch.Tensor) -> torch.Tensor:
-    n = base.shape[0]
+    n = _need_words(base, None, "base")
+    _need_words(exps, n, "exps", words=3)
     out = torch.empty_like(base)
     _check(lib().rlx_test_pow(base.data_ptr(), exps.data_ptr(), out.data_ptr(), n, _stream()), "rlx_test_pow")
     return out
 
 
 def test_to_ranlux(x: torch.Tensor):
-    n = x.shape[0]
+    n = _need_words(x, None, "x")
     d = torch.empty_like(x)
     carry = torch.empty((n,), dtype=torch.int32, device=x.device)
     _check(lib().rlx_test_to_ranlux(x.data_ptr(), d.data_ptr(), carry.data_ptr(), n, _stream()),
