@@ -114,16 +114,25 @@ int rlx_prepare(uint32_t p, void *stream);
  *   folded[(g * 21 + j) * 18 .. + 17] = A_p^(2^g) 2^(o_j) mod m, g <
  *     RLX_FOLD_G, j < 21, o_j the limb offsets 0, 28, ..., 280, 307, ..., 550
  *     (ten 28-bit, ten 27-bit and one 26-bit limb): the folded multiplier of
- *     2^g generator steps, X <- A_p^(2^g) X = sum_j limb_j(X) C_g[j]. */
+ *     2^g generator steps, X <- A_p^(2^g) X = sum_j limb_j(X) C_g[j].
+ *   windows16[(i * RLX_WIN16_COLS + j) * 18 .. + 17] = A_p^(j 65536^i) mod m
+ *     for i < RLX_WIN16_SEED_ROW0 (16-bit windows of a skip by k < 2^64
+ *     steps) and A_p^(2^96 j 65536^(i - RLX_WIN16_SEED_ROW0)) mod m for the
+ *     rows from RLX_WIN16_SEED_ROW0 on (those of a seed's exponent 2^96 id,
+ *     id < 2^64); i < RLX_WIN16_ROWS, j < RLX_WIN16_COLS (37.7 MB). */
 #define RLX_TAB_ROWS 40
 #define RLX_TAB_COLS 16
 #define RLX_SEED_ROW0 24
 #define RLX_FOLD_G 64
+#define RLX_WIN16_ROWS 8
+#define RLX_WIN16_COLS 65536
+#define RLX_WIN16_SEED_ROW0 4
 
 typedef struct rlx_engine_tables {
-    const uint32_t *windows;  /* RLX_TAB_ROWS * RLX_TAB_COLS * 18 words */
-    const uint32_t *folded;   /* RLX_FOLD_G * 21 * 18 words */
-    uint32_t p;               /* luxury level */
+    const uint32_t *windows;    /* RLX_TAB_ROWS * RLX_TAB_COLS * 18 words */
+    const uint32_t *folded;     /* RLX_FOLD_G * 21 * 18 words */
+    const uint32_t *windows16;  /* RLX_WIN16_ROWS * RLX_WIN16_COLS * 18 words */
+    uint32_t p;                 /* luxury level */
     uint32_t reserved;
 } rlx_engine_tables;
 

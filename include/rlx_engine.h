@@ -74,20 +74,29 @@ __device__ __forceinline__ void current_state(const rlx_engine& e, uint32_t (&x)
     }
 }
 
-/* x <- A x for A = product of table windows selected by the 4-bit digits of
- * the exponent k (windows rows row0, row0 + 1, ...: A_p^(j 16^i)). */
-__device__ __forceinline__ void pow_windows(uint32_t (&x)[rlx::NW], uint64_t k, const uint32_t* windows,
-                                            int row0) {
-    for (int nib = 0; nib < 16 && (k >> (4 * nib)) != 0; ++nib) {
-        const uint32_t v = (uint32_t)(k >> (4 * nib)) & 15u;
+/* x <- A x for A = product of the 16-bit window entries selected by the
+ * digits of the exponent k (rows row0, row0 + 1, ... of windows16:
+ * A_p^(j 65536^i), or its seed rows).  With from_one, x is 1 on entry and
+ * the first non-zero digit's entry is copied instead of multiplied. */
+__device__ __forceinline__ void pow_windows16(uint32_t (&x)[rlx::NW], uint64_t k, const uint32_t* w16, int row0,
+                                              bool from_one) {
+    for (int d = 0; d < 4 && (k >> (16 * d)) != 0; ++d) {
+        const uint32_t v = (uint32_t)(k >> (16 * d)) & 0xFFFFu;
         if (v == 0) continue;
-        const uint32_t* w = windows + ((size_t)(row0 + nib) * RLX_TAB_COLS + v) * rlx::NW;
-        uint32_t y[rlx::NW], r[rlx::NW];
+        const uint32_t* w = w16 + ((size_t)(row0 + d) * RLX_WIN16_COLS + v) * rlx::NW;
+        uint32_t y[rlx::NW];
 #pragma unroll
         for (int i = 0; i < rlx::NW; ++i) y[i] = w[i];
-        rlx::mulmod_generic(x, y, r);
+        if (from_one) {
 #pragma unroll
-        for (int i = 0; i < rlx::NW; ++i) x[i] = r[i];
+            for (int i = 0; i < rlx::NW; ++i) x[i] = y[i];
+            from_one = false;
+        } else {
+            uint32_t r[rlx::NW];
+            rlx::mulmod_generic(x, y, r);
+#pragma unroll
+            for (int i = 0; i < rlx::NW; ++i) x[i] = r[i];
+        }
     }
 }
 
@@ -156,20 +165,22 @@ __device__ __forceinline__ void rlx_engine_store(const rlx_engine& e, rlx_state*
 }
 
 /* Seed with stream id (section 2.4): X = A_p^(2^96 id), position 0 -- the
- * record rlx_init_streams writes for that id. */
+ * record rlx_init_streams writes for that id.  One table entry per non-zero
+ * 16-bit digit of id: ids below 2^16 are a copy. */
 __device__ __forceinline__ void rlx_engine_seed(rlx_engine& e, uint64_t id, const rlx_engine_tables& t) {
     uint32_t x[rlx::NW];
 #pragma unroll
     for (int k = 0; k < rlx::NW; ++k) x[k] = k == 0 ? 1u : 0u;
-    rlx_engine_detail::pow_windows(x, id, t.windows, RLX_SEED_ROW0);
+    rlx_engine_detail::pow_windows16(x, id, t.windows16, RLX_WIN16_SEED_ROW0, true);
     rlx_engine_detail::set_state(e, x, 0);
 }
 
-/* Skip k generator steps (12 k values), position unchanged (section 2.4). */
+/* Skip k generator steps (12 k values), position unchanged (section 2.4):
+ * one multiplication per non-zero 16-bit digit of k. */
 __device__ __forceinline__ void rlx_engine_skip(rlx_engine& e, uint64_t k, const rlx_engine_tables& t) {
     uint32_t x[rlx::NW];
     rlx_engine_detail::current_state(e, x);
-    rlx_engine_detail::pow_windows(x, k, t.windows, 0);
+    rlx_engine_detail::pow_windows16(x, k, t.windows16, 0, false);
     rlx_engine_detail::set_state(e, x, e.pos);
 }
 

@@ -281,7 +281,7 @@ def generate_f64_lcg52(states: torch.Tensor, count: int, p: int, out: torch.Tens
 class EngineTables(ctypes.Structure):
     """rlx_engine_tables: device addresses of a luxury level's tables, to be
     passed by value to kernels that use the device-side engine."""
-    _fields_ = [("windows", ctypes.c_void_p), ("folded", ctypes.c_void_p),
+    _fields_ = [("windows", ctypes.c_void_p), ("folded", ctypes.c_void_p), ("windows16", ctypes.c_void_p),
                 ("p", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 

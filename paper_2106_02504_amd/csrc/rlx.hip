@@ -711,6 +711,7 @@ int rlx_get_tables(uint32_t p, rlx_engine_tables* out, void* stream) {
   int rc = tables(p, as_stream(stream), &t);
   if (rc) return rc;
   out->windows = t.T;
+  out->windows16 = t.W;
   out->folded = t.C;
   out->p = p;
   out->reserved = 0;

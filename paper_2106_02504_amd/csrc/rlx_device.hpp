@@ -29,9 +29,10 @@ constexpr int FOLD_G = RLX_FOLD_G;
 constexpr size_t FOLD_ROW_WORDS = (size_t)NL * NW;  // one folded multiplier
 constexpr size_t FOLD_WORDS = (size_t)FOLD_G * FOLD_ROW_WORDS;
 constexpr int WIN_BITS = 16;
-constexpr int WIN_ROWS = 8;
-constexpr int WIN_COLS = 1 << WIN_BITS;
-constexpr int WIN_SEED_ROW0 = 4;
+constexpr int WIN_ROWS = RLX_WIN16_ROWS;
+constexpr int WIN_COLS = RLX_WIN16_COLS;
+constexpr int WIN_SEED_ROW0 = RLX_WIN16_SEED_ROW0;
+static_assert(WIN_COLS == 1 << WIN_BITS, "16-bit windows");
 constexpr size_t WIN_WORDS = (size_t)WIN_ROWS * WIN_COLS * NW;
 constexpr int BLOCK = 256;
 constexpr int FIELDS = 12;

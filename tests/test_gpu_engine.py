@@ -150,4 +150,4 @@ def test_engine_rejects_bad_records_and_args():
     with pytest.raises(rlx.RlxError):
         rlx.test_engine(a, 5, 23, "f64")
     t = rlx.get_tables(p)
-    assert t.windows and t.folded and t.p == p
+    assert t.windows and t.folded and t.windows16 and t.p == p
