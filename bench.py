@@ -142,6 +142,9 @@ def measured_traffic(kernel: str):
     return measured_counters(kernel).get("hbm_bytes_per_launch")
 
 
+SETTLE_STEPS = 100   # steps of this load after which the chip's clock has settled
+
+
 def device_info(torch, dev) -> dict:
     """What the runtime reports for the GPU the bench ran on (the roofline
     peaks use the published figures: 256 CUs, 2.4 GHz, 8 TB/s)."""
@@ -306,7 +309,7 @@ def main() -> int:
     # launch 100 on the kernel holds at one duration (+-1%).  The default
     # warm-up covers that; the timed steps then measure the sustained rate.
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=SETTLE_STEPS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=8192)
     ap.add_argument("--legs", default="ceilings,u64,normal,f32,lcg52,single,skip,engine,batch,serve",
@@ -386,6 +389,29 @@ def main() -> int:
     init_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_init]))
     total = N_STREAMS * DRAWS
     value = total / wall
+
+    # With fewer than 100 warm-up steps the timed steps above fall inside
+    # the power-management swing of the first ~50 ms of load.  The requested
+    # measurement stays the headline; this one is reported beside it: the
+    # same step after 100 untimed and over 200 timed steps.
+    sustained = None
+    if args.warmup < SETTLE_STEPS:
+        for _ in range(SETTLE_STEPS):
+            step()
+        torch.cuda.synchronize()
+        ev.clear()
+        ev_init.clear()
+        t0 = time.perf_counter()
+        for _ in range(200):
+            step()
+        torch.cuda.synchronize()
+        s_wall = (time.perf_counter() - t0) / 200
+        s_gen = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        s_bytes = total * 8 + N_STREAMS * 80 * 2
+        sustained = {"value": total / s_wall, "ms_per_step": s_wall * 1e3, "kernel_ms": round(s_gen, 4),
+                     "hbm_frac": round(s_bytes / (s_gen * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "note": f"{SETTLE_STEPS} untimed then 200 timed steps, because --warmup {args.warmup} "
+                             f"< {SETTLE_STEPS}"}
 
     # bit-exact check of the sampled streams against the oracle's values
     bit_exact = None
@@ -554,6 +580,7 @@ def main() -> int:
         "device": device_info(torch, dev),
         "roofline": roofline,
         "roofline_alu": roofline_alu,
+        "sustained": sustained,
         "valu_issue": valu_issue,
         "cpu_baseline": cpu,
         "legs": legs,
