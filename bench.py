@@ -85,6 +85,38 @@ def batch_sample(reqs, k=24, width=512):
     return out
 
 
+def serve_sample(n_requests: int, k=16, width=512):
+    """Requests of the serving leg's check run compared with the oracle:
+    their first and last `width` values.  The server hands each request the
+    next window of its stream in admission order (arrival order, index order
+    for ties), and the leg serves the same request list (the same stream ids
+    and counts) five times after a warm-up: three Poisson loads, the timed
+    capacity run and an untimed check run with every request arriving at
+    once, so every start is known in advance from the counts alone."""
+    import random
+    import workloads
+    warm = workloads.serve_requests(64, 1.0, seed=6)
+    runs = workloads.serve_requests(n_requests, 1.0)
+    cursor = {}
+    for r in warm:
+        cursor[r.stream_id] = cursor.get(r.stream_id, 0) + r.count
+    for _ in range(4):                        # the Poisson runs and the capacity run
+        for r in runs:
+            cursor[r.stream_id] = cursor.get(r.stream_id, 0) + r.count
+    starts = []
+    for r in runs:                            # the check run
+        starts.append(cursor.get(r.stream_id, 0))
+        cursor[r.stream_id] = starts[-1] + r.count
+    rng = random.Random(45)
+    out = []
+    for i in sorted(rng.sample(range(len(runs)), k)):
+        r = runs[i]
+        n = min(r.count, width)
+        rel = [0] + ([r.count - n] if r.count > n else [])
+        out.append((i, (r.stream_id, P, r.count, [(starts[i] + o, n) for o in rel])))
+    return out
+
+
 def oracle_checks(items, workers: int):
     ctx = mp.get_context("fork")
     with ctx.Pool(workers) as pool:
@@ -234,7 +266,7 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
                         "counts floor(2^(20U)) in [1, 2^20], one fused launch"}
 
 
-def serve_leg(rlx, torch, np, dev, plain_rate, args):
+def serve_leg(rlx, torch, np, dev, plain_rate, args, checks=None):
     """Poisson arrivals of requests of log-uniform size 10^3..10^8 from a pool
     of 10^6 streams (p = 2048), at 0.5, 0.8 and 0.95 of the plain kernel's
     measured rate divided by the mean request size."""
@@ -262,6 +294,27 @@ def serve_leg(rlx, torch, np, dev, plain_rate, args):
     summ = st.summary()
     res["capacity"] = {"doubles_per_s": summ["doubles_per_s"], "fraction_of_plain": summ["doubles_per_s"] / plain_rate,
                        "batches": summ["batches"], "makespan_s": summ["makespan_s"]}
+    # check run (untimed: the copies synchronise): the same load again, with
+    # sampled requests compared with oracle windows computed in the CPU leg
+    if checks is None:
+        res["capacity"].update(bit_exact_sample=None, sample=None)
+        srv.close()
+        return res
+    seen = {}
+
+    def grab(i, view):
+        if i in checks:
+            seen[i] = [(w, (view[w - int(st0[i]):w - int(st0[i]) + len(v)] * 2.0 ** 48).to(torch.int64)
+                        .cpu().numpy().view(np.uint64).tolist()) for w, v in checks[i]]
+
+    st0 = {i: min(w for w, _ in wins) for i, wins in checks.items()}   # offset 0 starts the request
+    st = srv.run([0.0] * len(reqs), [r.stream_id for r in reqs], [r.count for r in reqs], on_complete=grab)
+    starts = st.summary()["starts"]
+    exact = all(i in seen and all(got == want for (_, got), (_, want) in zip(seen[i], checks[i]))
+                for i in checks) and all(int(starts[i]) == st0[i] for i in checks)
+    res["capacity"].update(bit_exact_sample=exact,
+                           sample=f"check run after the capacity run: first and last 512 values of {len(checks)} "
+                                  f"requests against the oracle")
     srv.close()
     return res
 
@@ -337,9 +390,12 @@ def main() -> int:
     batch_reqs = workloads.batch_requests() if "batch" in wanted else None
     cpu = None
     checks = None
+    serve_checks = None
     if not args.no_cpu:
         if batch_reqs is not None:
             checks = oracle_checks(batch_sample(batch_reqs), min(16, os.cpu_count() or 1))
+        if "serve" in wanted:
+            serve_checks = oracle_checks(serve_sample(args.serve_requests), min(16, os.cpu_count() or 1))
         workers = min(16, os.cpu_count() or 1)
         ref, cpu_dt = cpu_baseline(args.cpu_streams, workers)
         cpu = {"value": args.cpu_streams * DRAWS / cpu_dt, "unit": "doubles/s", "cores": workers,
@@ -549,7 +605,7 @@ def main() -> int:
         legs["batch"] = batch_leg(rlx, torch, np, dev, batch_reqs, checks, args)
 
     if "serve" in wanted:
-        legs["serve"] = serve_leg(rlx, torch, np, dev, value, args)
+        legs["serve"] = serve_leg(rlx, torch, np, dev, value, args, serve_checks)
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
