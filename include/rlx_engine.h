@@ -216,7 +216,7 @@ __device__ __forceinline__ double rlx_engine_next_normal(rlx_engine& e, const rl
     rlx_engine_detail::pair_words(e, e.pos >> 1, w0, w1, w2);
     const double u1 = (double)(((uint64_t)(w1 & 0xFFFFu) << 32) | w0) * 0x1p-48;
     const double u2 = (double)(((uint64_t)(w2 >> 16) << 32) | __builtin_amdgcn_alignbit(w2, w1, 16)) * 0x1p-48;
-    const double r = sqrt(-2.0 * log1p(-u1));
+    const double r = sqrt(-2.0 * log(1.0 - u1));  /* 1 - u1 is exact */
     double sn, cs;
     sincospi(2.0 * u2, &sn, &cs);  /* the bulk kernels' evaluation, so the bits agree */
     const double z = r * ((e.pos & 1u) ? sn : cs);

@@ -171,7 +171,8 @@ __device__ __forceinline__ uint32_t number_f32_bits(uint32_t v) {
 // normals, Box-Muller on the pair: r = sqrt(-2 ln(1 - u1)) with u1 the even
 // field's double, and the even and odd positions get r cos(2 pi u2) and
 // r sin(2 pi u2), both from one sincospi (one range reduction); 1 - u1 is in
-// (0, 1] and 2 u2 is exact.  For float32 each position holds its two RANLUX
+// (0, 1] and exact (u1 is a multiple of 2^-48), so log of it is as accurate
+// as log1p(-u1) and cheaper; 2 u2 is exact.  For float32 each position holds its two RANLUX
 // numbers (bits 0..23 and 24..47 of the field), the older one in the low
 // 32 bits, i.e. first in memory.
 template <Out K>
@@ -193,7 +194,7 @@ __device__ __forceinline__ void pair_values(uint32_t w0, uint32_t w1, uint32_t w
       a = f64_bits(u1);
       b = f64_bits(u2);
     } else {
-      const double r = sqrt(-2.0 * log1p(-u1));
+      const double r = sqrt(-2.0 * log(1.0 - u1));
       double sn, cs;
       sincospi(2.0 * u2, &sn, &cs);
       a = f64_bits(r * cs);

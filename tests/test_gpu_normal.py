@@ -1,13 +1,13 @@
 """GPU parity of the Gaussian draws (rlx_generate_normal_f64) against the
 mpmath Box-Muller oracle.
 
-The device evaluates log1p, sqrt and cospi in binary64, each within a few ulp,
+The device evaluates log, sqrt and cospi in binary64, each within a few ulp,
 so values are compared under a tolerance rather than bit for bit:
 
     |gpu - oracle| <= 2^-49 |oracle| + 2^-70
 
 The relative part is 8 ulp of the result: the radius carries the errors of
-log1p (ocml, about 1 ulp) halved by the correctly rounded sqrt, the angle
+log (ocml, about 1 ulp, of the exact 1 - u1) halved by the correctly rounded sqrt, the angle
 factor is cospi of an exactly formed argument (about 1-2 ulp, relative also
 near its zeros because cospi reduces to sinpi there), and the product adds
 half an ulp; 8 ulp leaves a factor of two of margin.  The absolute floor
