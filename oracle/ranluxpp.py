@@ -105,8 +105,8 @@ RANLUX = SwbParams(BBITS, R, S)
 
 def mulmod(x: int, y: int) -> int:
     """(x * y) mod m, the canonical residue in [0, m): the product of two
-    576-bit numbers (section 2.1) reduced modulo m (section 2.2).  The paper
-    requires the reduced result to be smaller than m in all cases."""
+    576-bit numbers (section 2.1) reduced modulo m (section 2.2), whose
+    final correction always leaves a residue below m."""
     return (x * y) % M
 
 
