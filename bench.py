@@ -364,7 +364,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=SETTLE_STEPS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
-    ap.add_argument("--cpu-streams", type=int, default=8192)
+    ap.add_argument("--cpu-streams", type=int, default=16384)
     ap.add_argument("--legs", default="ceilings,u64,normal,f32,lcg52,single,skip,engine,batch,serve",
                     help="extra legs to time (comma list or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
@@ -401,7 +401,8 @@ def main() -> int:
         cpu = {"value": args.cpu_streams * DRAWS / cpu_dt, "unit": "doubles/s", "cores": workers,
                "kind": "oracle",
                "sample": f"first {args.cpu_streams} of the 65536 streams x {DRAWS} doubles, p={P} "
-                         f"({args.cpu_streams * DRAWS} doubles, {cpu_dt:.1f} s wall on {workers} processes)"}
+                         f"({args.cpu_streams * DRAWS} doubles, {cpu_dt:.1f} s wall on {workers} processes, "
+                         f"about {cpu_dt * workers:.0f} CPU-seconds)"}
 
     import numpy as np
     import torch
