@@ -23,3 +23,29 @@ def test_help_lists_the_contract_options():
     assert r.returncode == 0
     for opt in ("--gpus", "--steps", "--warmup", "--legs", "--no-cpu", "--batch-config"):
         assert opt in r.stdout
+
+
+def test_serve_sample_starts_follow_the_leg_order():
+    """The serving leg's oracle windows assume each request starts at its
+    stream's cursor after the warm-up, three Poisson loads and the capacity
+    run (the same request list each time), admitted in arrival order; here
+    that order is replayed as one first-come list over every run."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import workloads
+    n = 300
+    warm = workloads.serve_requests(64, 1.0, seed=6)
+    runs = workloads.serve_requests(n, 1.0)
+    seq = warm + runs * 5
+    cur, start = {}, []
+    for r in seq:
+        start.append(cur.get(r.stream_id, 0))
+        cur[r.stream_id] = start[-1] + r.count
+    check_run = start[len(warm) + 4 * n:]
+    sample = bench.serve_sample(n)
+    assert len(sample) == 16
+    for i, (sid, p, count, wins) in sample:
+        assert sid == runs[i].stream_id and count == runs[i].count and p == bench.P
+        assert wins[0][0] == check_run[i]                        # the request's first value
+        for w, m in wins:                                        # windows stay inside the request
+            assert check_run[i] <= w and w + m <= check_run[i] + count and m == min(512, count)
