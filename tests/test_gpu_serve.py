@@ -89,8 +89,8 @@ def test_serve_full_size_sampled():
     """The serving workload at its real size: a pool of 10^6 streams at
     p = 2048, request sizes floor(10^(3 + 5 U)) (up to 10^8 values), Poisson
     arrivals; 150 requests.  Requests of at most 10^5 values are checked
-    whole against the oracle, larger ones on their first, last and two
-    random windows of 512 values; every request's start is its stream's
+    whole against the oracle, larger ones on their first, last and eight
+    random windows of 1024 values; every request's start is its stream's
     cursor in arrival order."""
     import workloads
     reqs = workloads.serve_requests(150, 20000.0, seed=11)
@@ -107,8 +107,9 @@ def test_serve_full_size_sampled():
         if c <= 100_000:
             got[r] = [(0, view.cpu().numpy())]
         else:
-            offs = [0, c - 512, rng.randrange(c - 512), rng.randrange(c - 512)]
-            got[r] = [(o, view[o:o + 512].cpu().numpy()) for o in offs]
+            w = 1024
+            offs = [0, c - w] + [rng.randrange(c - w) for _ in range(8)]
+            got[r] = [(o, view[o:o + w].cpu().numpy()) for o in offs]
 
     stats = srv.run(arrival, stream_id, count, on_complete=check)
     start = fifo_starts(stream_id, count, arrival)
