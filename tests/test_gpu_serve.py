@@ -125,3 +125,29 @@ def test_serve_full_size_sampled():
             checked += len(vals)
     assert checked > 10 ** 5
     srv.close()
+
+
+def test_serve_zero_size_and_oversize_requests():
+    # zero-value requests are served (empty output, cursor unchanged) in the
+    # mix; a request larger than the arena is refused before anything runs
+    n, p, pool = 40, 24, 4
+    stream_id = np.array([k % pool for k in range(n)], dtype=np.uint64)
+    count = np.array([0 if k % 5 == 0 else 100 + 37 * k for k in range(n)], dtype=np.uint64)
+    arrival = np.zeros(n)
+    srv = Server(pool=pool, p=p, arena_values=1 << 14, slots=2, lanes=8, seg_blocks=16)
+    with pytest.raises(ValueError):
+        srv.run([0.0], [0], [(1 << 14) + 1])
+    assert int(srv.cursor.sum()) == 0             # the refused request moved nothing
+    stats, outs = srv.run(arrival, stream_id, count, keep_outputs=True)
+    start = fifo_starts(stream_id, count, arrival)
+    assert np.array_equal(stats.extra["starts"], start)
+    assert np.isfinite(stats.latencies_ms).all()
+    for k in range(n):
+        assert outs[k].size == int(count[k])
+        if count[k]:
+            exp = O.window(O.seed(int(stream_id[k]), p), p, int(start[k]), int(count[k]))
+            assert (outs[k] * 2.0 ** 48).astype(np.int64).tolist() == exp, k
+    # a batch made only of zero-value requests completes too
+    stats = srv.run(np.zeros(3), [1, 2, 3], [0, 0, 0])
+    assert stats.batches >= 1 and np.isfinite(stats.latencies_ms).all()
+    srv.close()
