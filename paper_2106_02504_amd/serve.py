@@ -136,6 +136,23 @@ class Server:
         for pl in self.plans:
             pl.close()
 
+    def snapshot(self) -> dict:
+        """Everything that fixes the values of later requests: the level, the
+        pool size and the per-stream cursors (the device records stay at
+        their seeds, so they need not be saved).  Plain numbers and a numpy
+        array, safe to store as raw bytes; call it between runs."""
+        return {"p": self.p, "pool": self.pool, "cursor": self.cursor.copy()}
+
+    def restore(self, snap: dict) -> None:
+        """Continue from a snapshot of a server with the same level and pool:
+        later requests get the values they would have had on that server."""
+        if int(snap["p"]) != self.p or int(snap["pool"]) != self.pool:
+            raise ValueError("snapshot of a different level or pool size")
+        cur = np.asarray(snap["cursor"], dtype=np.uint64)
+        if cur.shape != self.cursor.shape:
+            raise ValueError("snapshot cursor array does not match the pool")
+        self.cursor = cur.copy()
+
     def run(self, arrival_s, stream_id, count, keep_outputs: bool = False, max_batch: int = 4096,
             on_complete=None):
         """Serve the requests (arrival times in seconds from now, stream ids,

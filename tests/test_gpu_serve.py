@@ -151,3 +151,31 @@ def test_serve_zero_size_and_oversize_requests():
     stats = srv.run(np.zeros(3), [1, 2, 3], [0, 0, 0])
     assert stats.batches >= 1 and np.isfinite(stats.latencies_ms).all()
     srv.close()
+
+
+def test_serve_snapshot_restore_continues_the_streams():
+    # a server stopped after some requests and restored in a new server
+    # (cursors saved as raw bytes) hands out the same windows as one server
+    # that serves every request
+    rng = np.random.default_rng(21)
+    n, p, pool = 80, 794, 8
+    stream_id = rng.integers(0, pool, size=n).astype(np.uint64)
+    count = np.floor(10.0 ** (1 + 3 * rng.random(n))).astype(np.uint64)
+    arrival = np.zeros(n)
+    one = Server(pool=pool, p=p, arena_values=1 << 18, slots=2, lanes=8, seg_blocks=32)
+    _, ref = one.run(arrival, stream_id, count, keep_outputs=True)
+    one.close()
+    a = Server(pool=pool, p=p, arena_values=1 << 18, slots=2, lanes=8, seg_blocks=32)
+    _, first = a.run(arrival[:30], stream_id[:30], count[:30], keep_outputs=True)
+    snap = a.snapshot()
+    raw = snap["cursor"].tobytes()
+    a.close()
+    b = Server(pool=pool, p=p, arena_values=1 << 18, slots=3, lanes=16, seg_blocks=64)
+    b.restore({"p": p, "pool": pool, "cursor": np.frombuffer(raw, dtype=np.uint64)})
+    _, rest = b.run(arrival[30:], stream_id[30:], count[30:], keep_outputs=True)
+    for k in range(n):
+        got = first[k] if k < 30 else rest[k - 30]
+        assert np.array_equal(got, ref[k]), k
+    with pytest.raises(ValueError):
+        b.restore({"p": 24, "pool": pool, "cursor": snap["cursor"]})
+    b.close()
