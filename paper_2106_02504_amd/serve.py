@@ -85,8 +85,11 @@ class ServeStats:
     extra: dict = field(default_factory=dict)
 
     def summary(self) -> dict:
-        lat = self.latencies_ms
-        return {"requests": int(lat.size), "values": int(self.values),
+        # cancelled requests have no latency (NaN) and are left out
+        lat = self.latencies_ms[np.isfinite(self.latencies_ms)]
+        if lat.size == 0:
+            lat = np.zeros(1)
+        return {"requests": int(np.isfinite(self.latencies_ms).sum()), "values": int(self.values),
                 "doubles_per_s": self.values / self.makespan_s if self.makespan_s > 0 else 0.0,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
@@ -154,13 +157,18 @@ class Server:
         self.cursor = cur.copy()
 
     def run(self, arrival_s, stream_id, count, keep_outputs: bool = False, max_batch: int = 4096,
-            on_complete=None):
+            on_complete=None, cancel_s=None):
         """Serve the requests (arrival times in seconds from now, stream ids,
         counts), in real time.  Returns ServeStats (and, with keep_outputs,
         a list of host arrays holding each request's values).  on_complete,
         if given, is called as on_complete(request index, device view of its
         values) when its batch has finished, before the arena space is
-        reused (the view is only valid during the call)."""
+        reused (the view is only valid during the call).  cancel_s, if
+        given, holds a deadline per request (seconds from now; inf or NaN for
+        none): a request still waiting for admission at its deadline is
+        dropped -- it gets no values, its stream's cursor does not move, and
+        its latency, start and output stay empty (NaN, 0, None).  A request
+        already admitted is served."""
         arrival_s = np.asarray(arrival_s, dtype=np.float64)
         stream_id = np.asarray(stream_id, dtype=np.uint64)
         count = np.asarray(count, dtype=np.uint64)
@@ -177,7 +185,13 @@ class Server:
         free_slots = deque(range(self.slots))
         nxt = 0
         batches = max_inflight = max_breq = peak = 0
-        values = int(count.sum())
+        cancel = None
+        if cancel_s is not None:
+            cancel = np.asarray(cancel_s, dtype=np.float64).copy()
+            if cancel.shape != (n,):
+                raise ValueError("cancel_s needs one deadline per request")
+            cancel[np.isnan(cancel)] = np.inf
+        cancelled = np.zeros(n, dtype=bool)
 
         torch.cuda.synchronize(self.device)
         ref = torch.cuda.Event(enable_timing=True)
@@ -190,6 +204,15 @@ class Server:
             while nxt < n and arrival_s[order[nxt]] <= now:
                 waiting.append(int(order[nxt]))
                 nxt += 1
+            # cancellations of requests not yet admitted
+            if cancel is not None and waiting:
+                keep = deque()
+                for r in waiting:
+                    if cancel[r] <= now:
+                        cancelled[r] = True
+                    else:
+                        keep.append(r)
+                waiting = keep
             # completions
             still = []
             for b in inflight:
@@ -264,8 +287,10 @@ class Server:
             elif not free_slots or (not waiting and inflight):
                 time.sleep(0)  # yield; completions are polled
         torch.cuda.synchronize(self.device)
+        values = int(count[~cancelled].sum())
         lat = done_ms - arrival_s * 1e3
-        makespan = float(np.nanmax(done_ms)) * 1e-3 - float(arrival_s.min()) if n else 0.0
+        served = np.isfinite(done_ms)
+        makespan = float(done_ms[served].max()) * 1e-3 - float(arrival_s.min()) if served.any() else 0.0
         stats = ServeStats(lat, done_ms * 1e-3, values, makespan, batches, max_inflight, max_breq, peak,
-                           extra={"starts": start})
+                           extra={"starts": start, "cancelled": int(cancelled.sum())})
         return (stats, outputs) if keep_outputs else stats

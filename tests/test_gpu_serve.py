@@ -179,3 +179,34 @@ def test_serve_snapshot_restore_continues_the_streams():
     with pytest.raises(ValueError):
         b.restore({"p": 24, "pool": pool, "cursor": snap["cursor"]})
     b.close()
+
+
+def test_serve_cancelled_requests_take_no_values():
+    # requests cancelled before admission get nothing and move no cursor:
+    # the others get exactly the windows they would get without them
+    rng = np.random.default_rng(31)
+    n, p, pool = 60, 218, 6
+    stream_id = rng.integers(0, pool, size=n).astype(np.uint64)
+    count = np.floor(10.0 ** (1 + 3 * rng.random(n))).astype(np.uint64)
+    arrival = np.zeros(n)
+    cancel = np.full(n, np.nan)
+    cancel[::4] = 0.0                              # due before the first admission
+    cancel[1::8] = 1e9                             # far in the future: served
+    srv = Server(pool=pool, p=p, arena_values=1 << 16, slots=2, lanes=8, seg_blocks=32)
+    stats, outs = srv.run(arrival, stream_id, count, keep_outputs=True, cancel_s=cancel)
+    gone = np.zeros(n, dtype=bool)
+    gone[::4] = True
+    assert stats.extra["cancelled"] == int(gone.sum())
+    assert np.isnan(stats.latencies_ms[gone]).all() and np.isfinite(stats.latencies_ms[~gone]).all()
+    assert stats.values == int(count[~gone].sum())
+    kept = np.flatnonzero(~gone)
+    start = fifo_starts(stream_id[kept], count[kept], arrival[kept])
+    assert np.array_equal(stats.extra["starts"][kept], start)
+    assert int(srv.cursor.sum()) == int(count[kept].sum())
+    for j, k in enumerate(kept):
+        exp = O.window(O.seed(int(stream_id[k]), p), p, int(start[j]), int(count[k]))
+        assert (outs[k] * 2.0 ** 48).astype(np.int64).tolist() == exp, k
+    assert all(outs[k] is None for k in np.flatnonzero(gone))
+    summ = stats.summary()
+    assert summ["requests"] == kept.size and np.isfinite(summ["p99_ms"])
+    srv.close()
