@@ -22,17 +22,21 @@
  *              (e.g. PyTorch tensors).  The library never allocates, frees or
  *              retains caller memory.  It owns only per-(device, p) constant
  *              tables (about 38 MB per luxury level and device, kept until
- *              the process exits), one error word per device and the
- *              descriptors of batch plans (rlx_plan_create ..
- *              rlx_plan_destroy).
+ *              the process exits), the descriptors of batch plans
+ *              (rlx_plan_create .. rlx_plan_destroy) and statically sized
+ *              device variables (one error word per device).
  *   Streams    `stream` is a hipStream_t passed as void*; NULL is the default
  *              stream.  Work runs on the current HIP device and is enqueued
  *              asynchronously: calls return before the GPU has finished, and
  *              faults surface at the caller's next synchronisation.  The first
  *              call with a new luxury level p on a device builds that level's
  *              tables on `stream` and waits for them (about a millisecond);
- *              call rlx_prepare() first when the caller must not block, e.g.
- *              before capturing a HIP graph.
+ *              call rlx_prepare() first when the caller must not block.  On a
+ *              stream under HIP graph capture that first call cannot allocate
+ *              or wait: it returns RLX_ECAPTURE and enqueues nothing.  Once
+ *              the level is prepared, the generate, seed and skip calls and
+ *              rlx_plan_generate_* allocate, wait and clear nothing, so they
+ *              can be captured.
  *   Errors     Functions return RLX_OK (0) or a positive error code; the
  *              library never aborts and never prints.  rlx_strerror() gives a
  *              message.  Invalid stream records found by a kernel (x >= m,
@@ -73,7 +77,9 @@ enum {
     RLX_EINVAL = 1,   /* bad argument: NULL with n > 0, p < 24, misalignment, overflow */
     RLX_EHIP = 2,     /* HIP runtime or launch error */
     RLX_ENOMEM = 3,   /* table allocation failed */
-    RLX_ESTATE = 4    /* a kernel found an invalid stream record */
+    RLX_ESTATE = 4,   /* a kernel found an invalid stream record */
+    RLX_ECAPTURE = 5  /* tables of a new luxury level requested on a stream
+                         under HIP graph capture (see rlx_prepare) */
 };
 
 /* Size limits of one generate call (2^35 doubles are 256 GiB, more than
@@ -160,6 +166,10 @@ int rlx_skip(rlx_state *states, uint64_t n, const uint64_t *steps,
 
 /* Uniform doubles (section 2.3).  For every record i (luxury level p), draw
  * `count` values into out[i * count + j], j < count, and advance the record.
+ * When the lanes of one record span several waves (rlx_lanes_per_stream
+ * above 64), the record is advanced by a second launch on `stream` after the
+ * draws, as rlx_skip_values would, so no lane can read a record that another
+ * has already advanced; this holds for every generate entry point below.
  * A value is a 48-bit field v of the step's RANLUX numbers, converted as
  * v * 2^-48 (exact; in [0, 1), 0 possible).  Field k of a step is bits
  * [48k, 48k + 48) of D = floor(X 2^576 / m), the 24 RANLUX numbers packed

@@ -26,6 +26,10 @@ using namespace rlx;
 
 namespace {
 
+// Error word of each device: RLX_ERR_* bits that kernels OR in when they
+// reject a record (read and cleared by rlx_check_errors).
+__device__ uint32_t g_err_word;
+
 // ---------------------------------------------------------------------------
 // tables
 
@@ -135,16 +139,19 @@ __global__ __launch_bounds__(BLOCK) void k_init(rlx_state* __restrict__ st, uint
 }
 
 // by_values = 0: skip `steps` generator steps (pos unchanged); 1: skip that
-// many values (pos + v = 12 k + pos', k steps, new pos').
+// many values of `per_step` values per step (pos + v = per_step k + pos',
+// k steps, new pos'): 12 for the 48-bit fields, 11 for the legacy 52-bit
+// values, whose records must have pos < 11.
 __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint64_t n,
                                                 const uint64_t* __restrict__ steps, uint64_t steps0,
                                                 uint32_t p, const uint32_t* __restrict__ W,
-                                                uint32_t* __restrict__ err, int by_values) {
+                                                uint32_t* __restrict__ err, int by_values, uint32_t per_step) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t x[NW], pos, sp;
   load_record(st, i, x, pos, sp);
-  const uint32_t bad = check_record(x, pos, sp, p);
+  uint32_t bad = check_record(x, pos, sp, p);
+  if (by_values && pos >= per_step) bad |= RLX_ERR_BAD_POS;
   if (bad) {
     atomicOr(err, bad);
     return;
@@ -152,9 +159,9 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
   uint64_t k = steps ? steps[i] : steps0;
   if (by_values) {
     const uint64_t v = k;
-    const uint32_t r = pos + (uint32_t)(v % FIELDS);
-    k = v / FIELDS + r / FIELDS;
-    pos = r % FIELDS;
+    const uint32_t r = pos + (uint32_t)(v % per_step);
+    k = v / per_step + r / per_step;
+    pos = r % per_step;
   }
   skip_windows(x, k, W);
   store_record(st, i, x, pos, sp);
@@ -177,8 +184,14 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
 // instruction writes contiguous runs of the output row instead of one value
 // per row per lane.  LGS = 0 is G = 1 (direct stores, no staging).
 //
-// The record is advanced eagerly: the lane holding block nadv writes it back
-// with pos = (pos + count) mod 12.
+// The record is advanced eagerly.  When its G lanes lie in one wave
+// (writeback != 0, G <= 64), the lane holding block nadv writes it back with
+// pos = (pos + count) mod 12: every lane of the wave read the record at entry,
+// before that store in program order.  Lanes of a record that spans several
+// waves may be dispatched in different rounds, and nothing orders one wave's
+// load after another wave's store, so then no lane writes the record
+// (writeback = 0) and the host advances it by a skip launch on the same
+// stream after this kernel.
 template <Out K, bool TRACE, int LGS>
 __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, uint32_t n,
                                                     uint64_t count, uint64_t* __restrict__ out,
@@ -186,7 +199,7 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
                                                     const uint32_t* __restrict__ ctabs,
                                                     const uint32_t* __restrict__ W, uint32_t lg,
                                                     uint32_t p, uint32_t* __restrict__ err,
-                                                    int force_general) {
+                                                    int force_general, int writeback) {
   // Per-lane state kept across the loop is x plus four 32-bit words (record
   // index, lane, pos, last block): the host limits n < 2^32 and
   // count <= RLX_MAX_COUNT, so record and block indices fit in 32 bits.
@@ -228,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
     if (!__any(live)) break;
     if (live) {
       if (TRACE) put_trace(trace + ((uint64_t)i * trace_steps + t) * 9, x);
-      if (t == nadv) store_record(st, i, x, (uint32_t)((pos + count) % FIELDS), p);
+      if (writeback && t == nadv) store_record(st, i, x, (uint32_t)((pos + count) % FIELDS), p);
     }
     uint64_t* const row = out + (uint64_t)i * count;
     if (!STAGED) {
@@ -260,9 +273,9 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
 // this earlier conversion and drops it as biased): value k of step t is bits
 // [52k, 52k + 52) of X_t, k < 11, as v 2^-52, and the record's pos counts
 // these values (0..10).  Same lane interleaving as k_generate (lane l takes
-// steps l, l + G, ...); no RANLUX conversion.  A lane's 11 values go through
-// an LDS slot so that each store instruction writes gs consecutive doubles
-// of the row.
+// steps l, l + G, ...) and the same write-back rule; no RANLUX conversion.
+// A lane's 11 values go through an LDS slot so that each store instruction
+// writes gs consecutive doubles of the row.
 
 constexpr int LCG52_VALUES = 11;
 
@@ -282,7 +295,7 @@ __global__ __launch_bounds__(BLOCK) void k_generate_lcg52(rlx_state* __restrict_
                                                           double* __restrict__ out,
                                                           const uint32_t* __restrict__ ctabs,
                                                           const uint32_t* __restrict__ W, uint32_t lg, uint32_t p,
-                                                          uint32_t* __restrict__ err) {
+                                                          uint32_t* __restrict__ err, int writeback) {
   constexpr uint32_t gs = 1u << LGS;  // lanes of a record inside one wave
   __shared__ double stage[BLOCK * LCG52_VALUES];
   const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
@@ -317,7 +330,7 @@ __global__ __launch_bounds__(BLOCK) void k_generate_lcg52(rlx_state* __restrict_
     const uint32_t t = l + (k << lg);
     const bool live = active && t <= nadv;
     if (!__any(live)) break;
-    if (live && t == nadv) store_record(st, i, x, (uint32_t)((pos + count) % LCG52_VALUES), p);
+    if (writeback && live && t == nadv) store_record(st, i, x, (uint32_t)((pos + count) % LCG52_VALUES), p);
 #pragma unroll
     for (int f = 0; f < LCG52_VALUES; ++f) slot[f] = lcg52_value(x, f);
     wave_sync();
@@ -474,7 +487,7 @@ namespace {
 
 std::mutex g_mu;
 std::map<std::pair<int, uint32_t>, host::Tables> g_tables;
-std::map<int, uint32_t*> g_err;
+std::map<int, uint32_t*> g_err;  // address of g_err_word on each device
 
 inline bool grid_for(uint64_t n, dim3* g) {
   const uint64_t blocks = (n + BLOCK - 1) / BLOCK;
@@ -490,7 +503,7 @@ int current_device(int* dev) { return hipGetDevice(dev) == hipSuccess ? RLX_OK :
 namespace rlx {
 namespace host {
 
-int error_word(hipStream_t s, uint32_t** out) {
+int error_word(hipStream_t, uint32_t** out) {
   int dev;
   if (current_device(&dev)) return RLX_EHIP;
   std::lock_guard<std::mutex> lk(g_mu);
@@ -499,20 +512,24 @@ int error_word(hipStream_t s, uint32_t** out) {
     *out = it->second;
     return RLX_OK;
   }
+  // the word is a device variable (zero when the code object loads, one per
+  // device): finding its address allocates nothing and enqueues nothing, so
+  // this is safe on a stream under capture
   uint32_t* w = nullptr;
-  if (hipMalloc(&w, sizeof(uint32_t)) != hipSuccess) return RLX_ENOMEM;
-  if (hipMemsetAsync(w, 0, sizeof(uint32_t), s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-    (void)hipFree(w);
+  if (hipGetSymbolAddress(reinterpret_cast<void**>(&w), HIP_SYMBOL(g_err_word)) != hipSuccess || !w)
     return RLX_EHIP;
-  }
   try {
     g_err[dev] = w;
   } catch (const std::bad_alloc&) {
-    (void)hipFree(w);
     return RLX_ENOMEM;
   }
   *out = w;
   return RLX_OK;
+}
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
 }
 
 int tables(uint32_t p, hipStream_t s, Tables* out) {
@@ -525,6 +542,9 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
     *out = it->second;
     return RLX_OK;
   }
+  // building allocates and waits on `s`, which a stream under capture
+  // must not do
+  if (capturing(s)) return RLX_ECAPTURE;
   Tables t;
   if (hipMalloc(&t.T, TAB_WORDS * sizeof(uint32_t)) != hipSuccess) return RLX_ENOMEM;
   if (hipMalloc(&t.C, FOLD_WORDS * sizeof(uint32_t)) != hipSuccess) {
@@ -609,6 +629,22 @@ int generate_args(const rlx_state* states, uint64_t n, uint64_t count, const voi
   return grid_for(n << *lg, grid) ? RLX_OK : RLX_EINVAL;
 }
 
+// After a generate launch without in-kernel write-back (records spanning
+// several waves): advance every record by the `count` values the launch drew,
+// `per_step` values per generator step, with a skip launch on the same
+// stream, so the records are written only after every lane has read them.
+// Records the generate kernel rejected are rejected here too (same checks,
+// same error bits) and stay unchanged.
+int advance_after(rlx_state* states, uint64_t n, uint64_t count, uint32_t per_step, int writeback, uint32_t p,
+                  const uint32_t* W, uint32_t* err, hipStream_t s) {
+  if (launch_status()) return RLX_EHIP;
+  if (writeback) return RLX_OK;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  k_skip<<<grid, BLOCK, 0, s>>>(states, n, nullptr, count, p, W, err, 1, per_step);
+  return launch_status();
+}
+
 template <Out K, bool TRACE>
 int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint64_t* trace,
                   uint64_t trace_steps, uint32_t p, void* stream, int force_general) {
@@ -632,16 +668,17 @@ int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint
   if (rc) return rc;
   uint64_t* o = reinterpret_cast<uint64_t*>(out);
   const uint32_t lgs = lg < 6 ? lg : 6;
+  const int writeback = lg <= 6;
 #define RLX_GEN(L)                                                                                    \
   case L:                                                                                             \
     k_generate<K, TRACE, L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, trace, trace_steps, t.C, t.W, lg, p, \
-                                                     err, force_general);                             \
+                                                     err, force_general, writeback);                  \
     break;
   switch (lgs) {
     RLX_GEN(0) RLX_GEN(1) RLX_GEN(2) RLX_GEN(3) RLX_GEN(4) RLX_GEN(5) RLX_GEN(6)
   }
 #undef RLX_GEN
-  return launch_status();
+  return advance_after(states, n, count, FIELDS, writeback, p, t.W, err, s);
 }
 
 int generate_lcg52_impl(rlx_state* states, uint64_t n, uint64_t count, double* out, uint32_t p, void* stream) {
@@ -658,15 +695,17 @@ int generate_lcg52_impl(rlx_state* states, uint64_t n, uint64_t count, double* o
   rc = error_word(s, &err);
   if (rc) return rc;
   const uint32_t lgs = lg < 6 ? lg : 6;
+  const int writeback = lg <= 6;
 #define RLX_GEN52(L)                                                                                  \
   case L:                                                                                             \
-    k_generate_lcg52<L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, out, t.C, t.W, lg, p, err); \
+    k_generate_lcg52<L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, out, t.C, t.W, lg, p, err, \
+                                               writeback);                                            \
     break;
   switch (lgs) {
     RLX_GEN52(0) RLX_GEN52(1) RLX_GEN52(2) RLX_GEN52(3) RLX_GEN52(4) RLX_GEN52(5) RLX_GEN52(6)
   }
 #undef RLX_GEN52
-  return launch_status();
+  return advance_after(states, n, count, LCG52_VALUES, writeback, p, t.W, err, s);
 }
 
 }  // namespace
@@ -680,6 +719,9 @@ const char* rlx_strerror(int code) {
     case RLX_EHIP: return "HIP runtime or launch error";
     case RLX_ENOMEM: return "device allocation failed";
     case RLX_ESTATE: return "invalid stream record found on the device";
+    case RLX_ECAPTURE:
+      return "the stream is being captured and this luxury level's tables are not built yet: call "
+             "rlx_prepare(p) before capturing";
     default: return "unknown error";
   }
 }
@@ -748,7 +790,7 @@ int rlx_skip(rlx_state* states, uint64_t n, const uint64_t* steps, uint64_t step
   uint32_t* err;
   rc = error_word(s, &err);
   if (rc) return rc;
-  k_skip<<<grid, BLOCK, 0, s>>>(states, n, steps, steps0, p, t.W, err, 0);
+  k_skip<<<grid, BLOCK, 0, s>>>(states, n, steps, steps0, p, t.W, err, 0, FIELDS);
   return launch_status();
 }
 
@@ -766,7 +808,7 @@ int rlx_skip_values(rlx_state* states, uint64_t n, const uint64_t* values, uint6
   uint32_t* err;
   rc = error_word(s, &err);
   if (rc) return rc;
-  k_skip<<<grid, BLOCK, 0, s>>>(states, n, values, values0, p, t.W, err, 1);
+  k_skip<<<grid, BLOCK, 0, s>>>(states, n, values, values0, p, t.W, err, 1, FIELDS);
   return launch_status();
 }
 

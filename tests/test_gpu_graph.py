@@ -80,3 +80,36 @@ def test_graph_of_generation_continues_the_streams():
             exp = O.window(seeds[i], p, (rep + 1) * count, count)
             assert (got[i] * 2.0 ** 48).astype(np.int64).tolist() == exp, (rep, i)
         torch.cuda.synchronize()
+
+
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
+def test_capture_before_a_level_is_prepared_is_refused_then_replays_after_prepare():
+    # p = 333 is used by no other test, so its tables do not exist yet: a
+    # capture that would have to build them (allocate and wait on the
+    # capturing stream) gets RLX_ECAPTURE and enqueues nothing; after
+    # rlx_prepare the same capture replays, each replay continuing the streams
+    from rlx_util import records_to_tensor
+    p, n, count = 333, 300, 100
+    st = records_to_tensor([(O.seed(40 + i, p), 0, p) for i in range(n)])
+    out = torch.empty((n, count), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(rlx.RlxError) as err:
+        with torch.cuda.graph(g):
+            rlx.generate_f64(st, count, p, out=out)
+    assert err.value.code == 5 and "rlx_prepare" in str(err.value)
+    torch.cuda.synchronize()
+    assert torch.equal(st, records_to_tensor([(O.seed(40 + i, p), 0, p) for i in range(n)]))
+    rlx.prepare(p)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        rlx.generate_f64(st, count, p, out=out)
+    sample = random.Random(5).sample(range(n), 5)
+    for rep in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for i in sample:
+            exp = O.window(O.seed(40 + i, p), p, rep * count, count)
+            assert (got[i] * 2.0 ** 48).astype(np.int64).tolist() == exp, (rep, i)

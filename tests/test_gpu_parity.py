@@ -393,6 +393,51 @@ def test_lanes_short_counts_and_general_path(G, lanes_reset):
         assert tensor_to_records(st_a) == fin
 
 
+def test_records_spanning_many_waves_advance_after_the_launch():
+    """16 streams x 2^24 values at the automatic lane count G = 65536: 2^20
+    lanes in 16 384 waves, more than the chip holds at once, so the lanes of
+    one record run in several dispatch rounds and every workgroup still has
+    blocks to draw (21 steps per lane).  The records must end at position
+    2^24 (advanced after every lane has read them), every stream's values
+    must match the oracle at its start, end and random windows, and a second
+    call must continue from the advanced records.  The same for the legacy
+    52-bit doubles, whose records count 11 values per step."""
+    import oracle.widths as W
+    p, n, count = 2048, 16, 1 << 24
+    assert rlx.lanes_per_stream(n, count) == 65536
+    rng = random.Random(110)
+    st = rlx.new_states(n)
+    rlx.init_streams(st, p, id0=500)
+    out = rlx.generate_f64(st, count, p)
+    torch.cuda.synchronize()
+    recs = tensor_to_records(st)
+    for i in range(n):
+        x0 = O.seed(500 + i, p)
+        assert recs[i] == O.state_at(x0, p, count) + (p,), i
+        for j in [0, count - 40] + rng.sample(range(count - 40), 6):
+            got = (out[i, j:j + 40] * 2.0 ** 48).to(torch.int64).cpu().numpy().tolist()
+            assert got == O.window(x0, p, j, 40), (i, j)
+    nxt = rlx.generate_u64(st, 29, p)
+    for i in range(n):
+        assert u64_list(nxt[i]) == O.window(O.seed(500 + i, p), p, count, 29), i
+    del out
+    st = rlx.new_states(n)
+    rlx.init_streams(st, p, id0=700)
+    out = rlx.generate_f64_lcg52(st, count, p)
+    torch.cuda.synchronize()
+    recs = tensor_to_records(st)
+    for i in range(n):
+        x0 = O.seed(700 + i, p)
+        steps, pos = divmod(count, 11)
+        assert recs[i] == (O.skip(x0, steps, p), pos, p), i
+        for j in [0, count - 30] + rng.sample(range(count - 30), 4):
+            s0, p0 = divmod(j, 11)
+            want = W.draws_lcg52(O.skip(x0, s0, p), p0, p, 30)[0]
+            assert out[i, j:j + 30].cpu().numpy().tolist() == want, (i, j)
+    del out
+    torch.cuda.empty_cache()
+
+
 def test_output_beyond_2pow32_elements():
     """Two records x (2^31 + 5) doubles: row 1 starts past element 2^31 and
     ends past 2^32 (34 GB of output), so every output offset needs 64 bits.
