@@ -271,6 +271,25 @@ int rlx_import_ranlux(rlx_state *states, uint64_t n, const uint64_t *packed,
 int rlx_set_lanes_per_stream(uint32_t lanes);
 uint32_t rlx_lanes_per_stream(uint64_t n, uint64_t count);
 
+/* How the generate calls (rlx_generate_f64, _u64, _f32, _normal_f64,
+ * _f64_trace and rlx_test_generate_u64_general) multiply the state by the
+ * constant A_p^G in each generator step (sections 2.1, 2.2).  Both are exact
+ * and give bit-identical values and records:
+ *   RLX_STEP_MFMA  (default) the product as a contraction of the state's 72
+ *                  bytes with the byte digits of A_p^G 256^i mod m on the
+ *                  int8 matrix cores (v_mfma_i32_32x32x32_i8: exact 32-bit
+ *                  sums of 8-bit products), then a carry chain and the
+ *                  reduction mod m on the vector ALU;
+ *   RLX_STEP_VALU  the product as 32-bit multiply-adds on the vector ALU
+ *                  with the reduction folded into the multiplier.
+ * rlx_set_step_kernel applies to all later calls in the process and returns
+ * RLX_EINVAL for any other value; rlx_step_kernel reports the current one.
+ * The legacy 52-bit doubles and the batch plans always use RLX_STEP_VALU. */
+#define RLX_STEP_MFMA 0
+#define RLX_STEP_VALU 1
+int rlx_set_step_kernel(int kind);
+int rlx_step_kernel(void);
+
 /* ---- batched generation ---------------------------------------------------
  * Many requests, each a window of one stream, in ONE launch that
  * fuses skip-ahead, generation and conversion.  A request reads its stream
@@ -398,6 +417,14 @@ int rlx_test_to_ranlux(const uint64_t *x, uint64_t *d, uint32_t *carry,
  *           rlx_generate_f32 writes for 2 count floats). */
 int rlx_test_engine(rlx_state *states, uint64_t n, uint64_t count,
                     double *out, uint32_t mode, uint32_t p, void *stream);
+
+/* out[i] = A_p^(2^g) x[i] mod m: one generator step by 2^g steps (g <
+ * RLX_FOLD_G) with the step kernel `kind` (RLX_STEP_MFMA or RLX_STEP_VALU)
+ * that the generate calls use, on arbitrary x[i] < m (sections 2.1, 2.2).
+ * general != 0 sends the final fold through its general branch.  Lanes past
+ * n run on x = 1 and store nothing. */
+int rlx_test_step(const uint64_t *x, uint64_t *out, uint64_t n, uint32_t p,
+                  uint32_t g, int kind, int general, void *stream);
 
 /* rlx_generate_u64 with every rare-case branch of the step and the
  * conversion taken by all lanes (the exact general code), so that the general

@@ -26,9 +26,10 @@ __all__ = [
     "RlxError", "lib", "new_states", "prepare", "init_streams", "skip",
     "generate_f64", "generate_u64", "generate_normal_f64", "generate_f64_trace", "check_errors",
     "EngineTables", "get_tables", "test_engine",
-    "set_lanes_per_stream", "lanes_per_stream", "skip_values", "export_ranlux", "import_ranlux", "REQUEST_DTYPE", "requests_array", "Plan", "plan_dry_run",
+    "set_lanes_per_stream", "lanes_per_stream", "set_step_kernel", "step_kernel", "STEP_MFMA", "STEP_VALU",
+    "skip_values", "export_ranlux", "import_ranlux", "REQUEST_DTYPE", "requests_array", "Plan", "plan_dry_run",
     "constants", "test_mulmod", "test_pow", "test_to_ranlux",
-    "test_generate_u64_general", "STATE_WORDS",
+    "test_generate_u64_general", "test_step", "STATE_WORDS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -60,6 +61,8 @@ _SIGS = {
     "rlx_check_errors": (_int, [_vp, ctypes.POINTER(_u32)]),
     "rlx_set_lanes_per_stream": (_int, [_u32]),
     "rlx_lanes_per_stream": (_u32, [_u64, _u64]),
+    "rlx_set_step_kernel": (_int, [_int]),
+    "rlx_step_kernel": (_int, []),
     "rlx_constants": (None, [ctypes.POINTER(_u32), ctypes.POINTER(_u32)]),
     "rlx_plan_create": (_int, [ctypes.POINTER(_vp), _vp, _u64, _u32, _u64, _u64, _vp]),
     "rlx_plan_update": (_int, [_vp, _vp, _u64, _vp]),
@@ -74,6 +77,7 @@ _SIGS = {
     "rlx_test_pow": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "rlx_test_to_ranlux": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "rlx_test_generate_u64_general": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
+    "rlx_test_step": (_int, [_vp, _vp, _u64, _u32, _u32, _int, _int, _vp]),
 }
 
 _lib = None
@@ -339,6 +343,21 @@ def lanes_per_stream(n: int, count: int) -> int:
     return int(lib().rlx_lanes_per_stream(n, count))
 
 
+STEP_MFMA = 0   # generator step on the int8 matrix cores (default)
+STEP_VALU = 1   # generator step as 32-bit multiply-adds on the vector ALU
+
+
+def set_step_kernel(kind: int) -> None:
+    """Choose how later generate calls multiply by A_p^G: STEP_MFMA or
+    STEP_VALU (bit-identical values and records)."""
+    _check(lib().rlx_set_step_kernel(kind), "rlx_set_step_kernel")
+
+
+def step_kernel() -> int:
+    """The current step kernel (STEP_MFMA or STEP_VALU)."""
+    return int(lib().rlx_step_kernel())
+
+
 def requests_array(state, start, count, p, out_offset=None) -> "_np.ndarray":
     """Build a host array of rlx_request from per-request sequences; output
     offsets default to the prefix sums of the counts."""
@@ -519,6 +538,17 @@ def test_pow(base: torch.Tensor, exps: torch.Tensor) -> torch.Tensor:
     _need_words(exps, n, "exps", words=3)
     out = torch.empty_like(base)
     _check(lib().rlx_test_pow(base.data_ptr(), exps.data_ptr(), out.data_ptr(), n, _stream()), "rlx_test_pow")
+    return out
+
+
+def test_step(x: torch.Tensor, p: int, g: int, kind: int = STEP_MFMA, general: bool = False) -> torch.Tensor:
+    """One generator step by 2^g steps (A_p^(2^g) x mod m) with the given
+    step kernel, on int64 [n, 9] states x < m."""
+    n = _need_words(x, None, "x")
+    out = torch.empty_like(x)
+    with torch.cuda.device(x.device):
+        _check(lib().rlx_test_step(x.data_ptr(), out.data_ptr(), n, p, g, kind, int(general), _stream()),
+               "rlx_test_step")
     return out
 
 

@@ -2,9 +2,10 @@
 //
 // Kernels (one lane per stream record unless noted):
 //   k_tab_base / k_tab_fill / k_tab_fold / k_tab_win   per-luxury-level tables
+//   k_tab_mf_c / k_tab_mf_k / k_tab_mf_frag          matrix-core operands of a step
 //   k_init                                 seeding        (section 2.4)
 //   k_skip                                 skip-ahead     (section 2.4)
-//   k_generate<U64|F64|NORMAL|F32, trace, LGS> draw values (sections 2.1-2.3)
+//   k_generate<U64|F64|NORMAL|F32, trace, LGS, MF> draw values (sections 2.1-2.3)
 //   k_generate_lcg52<LGS>                  legacy raw-LCG doubles (section 2.3)
 //   k_test_*                               generic arithmetic for tests
 // The batched kernel and its planner are in rlx_batch.hip.
@@ -21,6 +22,7 @@
 #include "rlx_arith.hpp"
 #include "rlx_device.hpp"
 #include "rlx_internal.hpp"
+#include "rlx_mfma.hpp"
 
 using namespace rlx;
 
@@ -105,6 +107,77 @@ __global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T,
   for (int k = 0; k < NW; ++k) pw[k] = (k == (bit >> 5)) ? (1u << (bit & 31)) : 0u;
   mulmod_generic(a, pw, r);
   store_words(C + (size_t)g * FOLD_ROW_WORDS + (size_t)j * NW, r);
+}
+
+// Matrix-core operands of a step by 2^g generator steps (rlx_mfma.hpp),
+// g < RLX_FOLD_G, in three launches:
+// C_i = A_p^(2^g) 256^i mod m for i < 72, one lane per (g, i): its words go
+// to cw (for the sums of k_tab_mf_k) and its balanced digits to column i of
+// bal[g].
+__global__ __launch_bounds__(64) void k_tab_mf_c(const uint32_t* __restrict__ T, uint32_t* __restrict__ cw,
+                                                 int8_t* __restrict__ bal) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= FOLD_G * MF_BYTES) return;
+  const int g = t / MF_BYTES, i = t % MF_BYTES;
+  uint32_t a[NW], pw[NW], r[NW];
+  load_words(T + ((size_t)(g >> 2) * TAB_COLS + (1u << (g & 3))) * NW, a);
+  // The words of 256^i pass through an empty asm so that the multiplication
+  // is compiled for arbitrary operands: specialised for these sparse ones
+  // (bits only at multiples of 8), the gfx950 code gave wrong products for
+  // i = 7, 14, 21, 35, 42, 49 while the same source built for the host was
+  // exact.
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    uint32_t v = (k == i / 4) ? (1u << (8 * (i % 4))) : 0u;
+    asm volatile("" : "+v"(v));
+    pw[k] = v;
+  }
+  mulmod_generic(a, pw, r);
+  store_words(cw + (size_t)t * NW, r);
+  int8_t d[MF_ROWS];
+  balanced_digits(r, d);
+  int8_t* col = bal + ((size_t)g * MF_COLS + i) * MF_ROWS;
+  for (int k = 0; k < MF_ROWS; ++k) col[k] = d[k];
+}
+
+// K = 128 sum_i C_i as an exact integer (below 2^590, 19 words), one lane
+// per g: its balanced digits are column MF_BYTES of bal[g].
+__global__ __launch_bounds__(64) void k_tab_mf_k(const uint32_t* __restrict__ cw, int8_t* __restrict__ bal) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= FOLD_G) return;
+  uint32_t s[NW + 1];
+  for (int k = 0; k <= NW; ++k) s[k] = 0;
+  for (int i = 0; i < MF_BYTES; ++i) {
+    const uint32_t* c = cw + ((size_t)g * MF_BYTES + i) * NW;
+    uint32_t cy = 0;
+    for (int k = 0; k < NW; ++k) s[k] = addc(s[k], c[k], cy);
+    s[NW] += cy;
+  }
+  for (int k = NW; k > 0; --k) s[k] = (s[k] << 7) | (s[k - 1] >> 25);
+  s[0] <<= 7;
+  int8_t d[MF_ROWS];
+  balanced_digits(s, d);
+  int8_t* col = bal + ((size_t)g * MF_COLS + MF_BYTES) * MF_ROWS;
+  for (int k = 0; k < MF_ROWS; ++k) col[k] = d[k];
+}
+
+// The A operands: lane l of fragment f = 3 mt + ks of level g holds, in its
+// 16 bytes j, the digit of output row 32 mt + (l mod 32) of the input column
+// mf_input_column(l div 32, ks, j), zero for a zero column.
+__global__ __launch_bounds__(64) void k_tab_mf_frag(const int8_t* __restrict__ bal, uint32_t* __restrict__ M) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= FOLD_G * MF_FRAGS * 64) return;
+  const int g = t / (MF_FRAGS * 64), f = (t / 64) % MF_FRAGS, l = t % 64;
+  const int mt = f / 3, ks = f % 3, h = l / 32, row = 32 * mt + l % 32;
+  for (int q = 0; q < 4; ++q) {
+    uint32_t word = 0;
+    for (int b = 0; b < 4; ++b) {
+      const int col = mf_input_column(h, ks, 4 * q + b);
+      const int8_t v = col < 0 ? (int8_t)0 : bal[((size_t)g * MF_COLS + col) * MF_ROWS + row];
+      word |= (uint32_t)(uint8_t)v << (8 * b);
+    }
+    M[(size_t)t * 4 + q] = word;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -192,11 +265,12 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
 // load after another wave's store, so then no lane writes the record
 // (writeback = 0) and the host advances it by a skip launch on the same
 // stream after this kernel.
-template <Out K, bool TRACE, int LGS>
-__global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, uint32_t n,
+template <Out K, bool TRACE, int LGS, bool MF>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_generate(rlx_state* __restrict__ st, uint32_t n,
                                                     uint64_t count, uint64_t* __restrict__ out,
                                                     uint64_t* __restrict__ trace, uint64_t trace_steps,
                                                     const uint32_t* __restrict__ ctabs,
+                                                    const uint32_t* __restrict__ mtabs,
                                                     const uint32_t* __restrict__ W, uint32_t lg,
                                                     uint32_t p, uint32_t* __restrict__ err,
                                                     int force_general, int writeback) {
@@ -234,6 +308,14 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
   // same for the whole wave)
   if (STAGED) skip_windows(x, l, W);
   const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * FOLD_ROW_WORDS;
+  // MF: the step's matrix-core A operands for A^G, this lane's 16 bytes of
+  // each of the nine fragments, held for the whole launch
+  mf_v4i af[MF_FRAGS];
+  if constexpr (MF) {
+    const mf_v4i* mt = reinterpret_cast<const mf_v4i*>(mtabs + (size_t)lg * MF_LEVEL_WORDS);
+#pragma unroll
+    for (int f = 0; f < MF_FRAGS; ++f) af[f] = mt[f * 64 + (threadIdx.x & 63)];
+  }
 
   for (uint32_t k = 0;; ++k) {
     const uint32_t t = l + (k << lg);
@@ -264,7 +346,13 @@ __global__ __launch_bounds__(BLOCK) void k_generate(rlx_state* __restrict__ st, 
       const int64_t jb = (int64_t)((uint64_t)(t - ls) * FIELDS) - (int64_t)pos;
       group_store<LGS>(stage, tid_blk, ls, jb, count, active, row);
     }
-    if (__any(live && t + (1u << lg) <= nadv)) step(x, constant_table(ctab), force, SgprBarrier());
+    if (__any(live && t + (1u << lg) <= nadv)) {
+      if constexpr (MF) {
+        mfma_step(x, af, force);
+      } else {
+        step(x, constant_table(ctab), force, SgprBarrier());
+      }
+    }
   }
 }
 
@@ -478,6 +566,32 @@ __global__ __launch_bounds__(BLOCK) void k_test_to_ranlux(const uint64_t* __rest
   carry[i] = ranlux_carry(x, d);
 }
 
+// One step by the folded multiplier of 2^g steps, with either step kernel,
+// on arbitrary states (the matrix-core step needs whole waves: lanes past n
+// step x = 1 and store nothing).
+template <bool MF>
+__global__ __launch_bounds__(BLOCK) void k_test_step(const uint64_t* __restrict__ xs, uint64_t* __restrict__ out,
+                                                     uint64_t n, const uint32_t* __restrict__ ctab,
+                                                     const uint32_t* __restrict__ mtab, int general) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t x[NW];
+  if (i < n) {
+    load9(xs + i * 9, x);
+  } else {
+    set_one(x);
+  }
+  if constexpr (MF) {
+    mf_v4i af[MF_FRAGS];
+    const mf_v4i* mt = reinterpret_cast<const mf_v4i*>(mtab);
+#pragma unroll
+    for (int f = 0; f < MF_FRAGS; ++f) af[f] = mt[f * 64 + (threadIdx.x & 63)];
+    mfma_step(x, af, general != 0);
+  } else {
+    step(x, constant_table(ctab), general != 0, SgprBarrier());
+  }
+  if (i < n) store9(out + i * 9, x);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -551,9 +665,23 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
     (void)hipFree(t.T);
     return RLX_ENOMEM;
   }
-  if (hipMalloc(&t.W, WIN_WORDS * sizeof(uint32_t)) != hipSuccess) {
+  // the matrix-core operands, and two staging buffers freed after the build:
+  // the words of the C_i and their balanced digits
+  uint32_t* cw = nullptr;
+  int8_t* bal = nullptr;
+  auto release = [&]() {
     (void)hipFree(t.T);
     (void)hipFree(t.C);
+    (void)hipFree(t.W);
+    (void)hipFree(t.M);
+    (void)hipFree(cw);
+    (void)hipFree(bal);
+  };
+  if (hipMalloc(&t.W, WIN_WORDS * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&t.M, (size_t)FOLD_G * MF_LEVEL_WORDS * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&cw, (size_t)FOLD_G * MF_BYTES * NW * sizeof(uint32_t)) != hipSuccess ||
+      hipMalloc(&bal, (size_t)FOLD_G * MF_COLS * MF_ROWS) != hipSuccess) {
+    release();
     return RLX_ENOMEM;
   }
   k_tab_base<<<1, 64, 0, s>>>(t.T, p);
@@ -561,18 +689,21 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
   k_tab_fill<<<(fill + 63) / 64, 64, 0, s>>>(t.T);
   k_tab_fold<<<FOLD_G, 64, 0, s>>>(t.T, t.C);
   k_tab_win<<<(WIN_ROWS * WIN_COLS + 63) / 64, 64, 0, s>>>(t.T, t.W);
+  k_tab_mf_c<<<(FOLD_G * MF_BYTES + 63) / 64, 64, 0, s>>>(t.T, cw, bal);
+  k_tab_mf_k<<<(FOLD_G + 63) / 64, 64, 0, s>>>(cw, bal);
+  k_tab_mf_frag<<<FOLD_G * MF_FRAGS, 64, 0, s>>>(bal, t.M);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-    (void)hipFree(t.T);
-    (void)hipFree(t.C);
-    (void)hipFree(t.W);
+    release();
     return RLX_EHIP;
   }
+  (void)hipFree(cw);
+  (void)hipFree(bal);
+  cw = nullptr;
+  bal = nullptr;
   try {
     g_tables[key] = t;
   } catch (const std::bad_alloc&) {
-    (void)hipFree(t.T);
-    (void)hipFree(t.C);
-    (void)hipFree(t.W);
+    release();
     return RLX_ENOMEM;
   }
   *out = t;
@@ -587,6 +718,7 @@ using namespace rlx::host;
 namespace {
 
 std::atomic<uint32_t> g_lanes_override{0};
+std::atomic<int> g_step_kind{RLX_STEP_MFMA};
 
 // Lanes per record: the largest power of two G <= RLX_MAX_LANES such that
 // the launch stays within sixteen waves per SIMD (2^20 lanes on 256 CUs) and
@@ -669,10 +801,16 @@ int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint
   uint64_t* o = reinterpret_cast<uint64_t*>(out);
   const uint32_t lgs = lg < 6 ? lg : 6;
   const int writeback = lg <= 6;
+  const bool mf = g_step_kind.load(std::memory_order_relaxed) == RLX_STEP_MFMA;
 #define RLX_GEN(L)                                                                                    \
   case L:                                                                                             \
-    k_generate<K, TRACE, L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, trace, trace_steps, t.C, t.W, lg, p, \
-                                                     err, force_general, writeback);                  \
+    if (mf) {                                                                                         \
+      k_generate<K, TRACE, L, true><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, trace, trace_steps, t.C, \
+                                                            t.M, t.W, lg, p, err, force_general, writeback); \
+    } else {                                                                                          \
+      k_generate<K, TRACE, L, false><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, trace, trace_steps, t.C, \
+                                                             t.M, t.W, lg, p, err, force_general, writeback); \
+    }                                                                                                 \
     break;
   switch (lgs) {
     RLX_GEN(0) RLX_GEN(1) RLX_GEN(2) RLX_GEN(3) RLX_GEN(4) RLX_GEN(5) RLX_GEN(6)
@@ -887,6 +1025,14 @@ int rlx_set_lanes_per_stream(uint32_t lanes) {
 
 uint32_t rlx_lanes_per_stream(uint64_t n, uint64_t count) { return lanes_for(n, count); }
 
+int rlx_set_step_kernel(int kind) {
+  if (kind != RLX_STEP_MFMA && kind != RLX_STEP_VALU) return RLX_EINVAL;
+  g_step_kind.store(kind, std::memory_order_relaxed);
+  return RLX_OK;
+}
+
+int rlx_step_kernel(void) { return g_step_kind.load(std::memory_order_relaxed); }
+
 int rlx_check_errors(void* stream, uint32_t* flags) {
   hipStream_t s = as_stream(stream);
   uint32_t* err;
@@ -915,6 +1061,27 @@ int rlx_test_pow(const uint64_t* base, const uint64_t* exps, uint64_t* out, uint
   dim3 grid;
   if (!grid_for(n, &grid)) return RLX_EINVAL;
   k_test_pow<<<grid, BLOCK, 0, as_stream(stream)>>>(base, exps, out, n);
+  return launch_status();
+}
+
+int rlx_test_step(const uint64_t* x, uint64_t* out, uint64_t n, uint32_t p, uint32_t g, int kind, int general,
+                  void* stream) {
+  if (n == 0) return RLX_OK;
+  if (!x || !out || !valid_p(p) || g >= (uint32_t)FOLD_G) return RLX_EINVAL;
+  if (kind != RLX_STEP_MFMA && kind != RLX_STEP_VALU) return RLX_EINVAL;
+  dim3 grid;
+  if (!grid_for(n, &grid)) return RLX_EINVAL;
+  hipStream_t s = as_stream(stream);
+  Tables t;
+  int rc = tables(p, s, &t);
+  if (rc) return rc;
+  const uint32_t* ct = t.C + (size_t)g * FOLD_ROW_WORDS;
+  const uint32_t* mt = t.M + (size_t)g * MF_LEVEL_WORDS;
+  if (kind == RLX_STEP_MFMA) {
+    k_test_step<true><<<grid, BLOCK, 0, s>>>(x, out, n, ct, mt, general);
+  } else {
+    k_test_step<false><<<grid, BLOCK, 0, s>>>(x, out, n, ct, mt, general);
+  }
   return launch_status();
 }
 

@@ -15,6 +15,7 @@ struct Tables {
   uint32_t* T = nullptr;  // TAB_WORDS words
   uint32_t* C = nullptr;  // FOLD_WORDS words
   uint32_t* W = nullptr;  // WIN_WORDS words
+  uint32_t* M = nullptr;  // RLX_FOLD_G * MF_LEVEL_WORDS words: matrix-core step operands
 };
 
 inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }

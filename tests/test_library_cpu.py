@@ -138,3 +138,16 @@ def test_plan_capacity_limit(rlx):
     assert lib.rlx_plan_create(ctypes.byref(h), req.ctypes.data, 1, 8, 64, 1 << 33, None) == 1
     assert not h.value
     assert lib.rlx_plan_create(None, req.ctypes.data, 1, 8, 64, 0, None) == 1
+
+
+def test_step_kernel_choice(rlx):
+    # the step kernel switch: two kinds, anything else rejected, default MFMA
+    lib = rlx.lib()
+    assert lib.rlx_step_kernel() == rlx.STEP_MFMA == 0
+    assert lib.rlx_set_step_kernel(2) == 1 and lib.rlx_set_step_kernel(-1) == 1
+    assert lib.rlx_set_step_kernel(rlx.STEP_VALU) == 0 and lib.rlx_step_kernel() == rlx.STEP_VALU
+    assert lib.rlx_set_step_kernel(rlx.STEP_MFMA) == 0 and lib.rlx_step_kernel() == rlx.STEP_MFMA
+    # invalid arguments of the step test hook fail before any device work
+    assert lib.rlx_test_step(None, None, 5, 2048, 0, 0, 0, None) == 1
+    assert lib.rlx_test_step(ctypes.c_void_p(16), ctypes.c_void_p(16), 5, 2048, 64, 0, 0, None) == 1
+    assert lib.rlx_test_step(ctypes.c_void_p(16), ctypes.c_void_p(16), 5, 2048, 0, 2, 0, None) == 1
