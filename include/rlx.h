@@ -78,8 +78,10 @@ enum {
     RLX_EHIP = 2,     /* HIP runtime or launch error */
     RLX_ENOMEM = 3,   /* table allocation failed */
     RLX_ESTATE = 4,   /* a kernel found an invalid stream record */
-    RLX_ECAPTURE = 5  /* tables of a new luxury level requested on a stream
+    RLX_ECAPTURE = 5, /* tables of a new luxury level requested on a stream
                          under HIP graph capture (see rlx_prepare) */
+    RLX_ESCRATCH = 6  /* request beyond the library's static device array
+                         (rlx_build_tables_static) */
 };
 
 /* Size limits of one generate call (2^35 doubles are 256 GiB, more than
@@ -140,7 +142,49 @@ typedef struct rlx_engine_tables {
     const uint32_t *windows16;  /* RLX_WIN16_ROWS * RLX_WIN16_COLS * 18 words */
     uint32_t p;                 /* luxury level */
     uint32_t reserved;
+    const uint32_t *mfma;       /* RLX_FOLD_G * RLX_MFMA_ROW_WORDS words: the
+                                   matrix-core operands of a step by 2^g
+                                   steps (not used by the engine) */
 } rlx_engine_tables;
+
+/* Words of one step size's matrix-core operands: nine A operands of
+ * v_mfma_i32_32x32x32_i8 (three tiles of 32 output digits by three steps of
+ * 32 input bytes), 64 lanes x 16 bytes each.  Lane l of operand 3 t + s
+ * holds, in byte j, the balanced base-256 digit of row 32 t + (l mod 32) of
+ * A_p^(2^g) 256^i mod m, where i is the input byte the generate kernels place
+ * at (l div 32, j) of step s, or of K = 128 sum_i A_p^(2^g) 256^i for the
+ * constant input, or 0. */
+#define RLX_MFMA_ROW_WORDS (9u * 64u * 4u)
+
+/* Size of the static device array behind rlx_build_tables_static: the
+ * staging of every step size's matrix-core operands (RLX_FOLD_G x (72 x 72
+ * bytes of words + 73 x 96 balanced digits)). */
+#define RLX_STATIC_SCRATCH_BYTES 780288u
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): build the tables
+ * of luxury level p that rlx_prepare and rlx_get_tables build, into device
+ * buffers the caller owns, allocating nothing.  The staging of the
+ * matrix-core operands (the library's own build allocates and frees it) lives
+ * in a static device array of RLX_STATIC_SCRATCH_BYTES that each device holds
+ * from the library's first use of it until the process exits.
+ *   rows       number of step sizes 2^g built, g < rows, 1 <= rows <=
+ *              RLX_FOLD_G (RLX_ESCRATCH beyond: more staging than the
+ *              array holds; RLX_EINVAL for 0)
+ *   windows    RLX_TAB_ROWS * RLX_TAB_COLS * 18 words, as rlx_engine_tables
+ *   folded     rows * 21 * 18 words, as rlx_engine_tables (rows g < rows)
+ *   windows16  RLX_WIN16_ROWS * RLX_WIN16_COLS * 18 words, as
+ *              rlx_engine_tables
+ *   mfma       rows * RLX_MFMA_ROW_WORDS words, 16-byte aligned, as
+ *              rlx_engine_tables (rows g < rows)
+ * The values equal those of rlx_get_tables for the same p.  The build is
+ * enqueued on `stream` and the call returns without waiting, so it may be
+ * captured.  Every call on one device stages through that device's one
+ * array: calls that overlap on a device (other streams, or host threads)
+ * race and must be ordered by the caller.  Words of folded and mfma past
+ * `rows` are not written. */
+int rlx_build_tables_static(uint32_t p, uint32_t rows, uint32_t *windows, uint32_t *folded,
+                            uint32_t *windows16, uint32_t *mfma, void *stream);
 
 /* Addresses of the tables of level p on the current device, for kernels
  * that run the device-side engine of rlx_engine.h (the paper's GPU use, one

@@ -25,7 +25,7 @@ import torch  # load torch's HIP runtime first: librlx.so binds to the same one
 __all__ = [
     "RlxError", "lib", "new_states", "prepare", "init_streams", "skip",
     "generate_f64", "generate_u64", "generate_normal_f64", "generate_f64_trace", "check_errors",
-    "EngineTables", "get_tables", "test_engine",
+    "EngineTables", "get_tables", "build_tables_static", "table_words", "test_engine",
     "set_lanes_per_stream", "lanes_per_stream", "set_step_kernel", "step_kernel", "STEP_MFMA", "STEP_VALU",
     "skip_values", "export_ranlux", "import_ranlux", "REQUEST_DTYPE", "requests_array", "Plan", "plan_dry_run",
     "constants", "test_mulmod", "test_pow", "test_to_ranlux",
@@ -56,6 +56,7 @@ _SIGS = {
     "rlx_generate_f32": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_generate_f64_lcg52": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_get_tables": (_int, [_u32, _vp, _vp]),
+    "rlx_build_tables_static": (_int, [_u32, _u32, _vp, _vp, _vp, _vp, _vp]),
     "rlx_test_engine": (_int, [_vp, _u64, _u64, _vp, _u32, _u32, _vp]),
     "rlx_generate_f64_trace": (_int, [_vp, _u64, _u64, _vp, _vp, _u64, _u32, _vp]),
     "rlx_check_errors": (_int, [_vp, ctypes.POINTER(_u32)]),
@@ -286,7 +287,7 @@ class EngineTables(ctypes.Structure):
     """rlx_engine_tables: device addresses of a luxury level's tables, to be
     passed by value to kernels that use the device-side engine."""
     _fields_ = [("windows", ctypes.c_void_p), ("folded", ctypes.c_void_p), ("windows16", ctypes.c_void_p),
-                ("p", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("p", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("mfma", ctypes.c_void_p)]
 
 
 def get_tables(p: int, device=None) -> EngineTables:
@@ -295,6 +296,27 @@ def get_tables(p: int, device=None) -> EngineTables:
     with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
         _check(lib().rlx_get_tables(p, ctypes.byref(t), _stream()), "rlx_get_tables")
     return t
+
+
+def table_words(rows: int = 64) -> dict:
+    """Sizes in 32-bit words of a level's tables (windows, folded, windows16,
+    mfma) with `rows` step sizes."""
+    return {"windows": 40 * 16 * 18, "folded": rows * 21 * 18, "windows16": 8 * 65536 * 18,
+            "mfma": rows * 9 * 64 * 4}
+
+
+def build_tables_static(p: int, rows: int, windows: torch.Tensor, folded: torch.Tensor,
+                        windows16: torch.Tensor, mfma: torch.Tensor) -> None:
+    """rlx_build_tables_static: build level p's tables into caller-owned
+    int32 device tensors (sizes from table_words(rows)) on the current
+    stream, allocating nothing; staging in the library's static array."""
+    need = table_words(rows)
+    for name, t in (("windows", windows), ("folded", folded), ("windows16", windows16), ("mfma", mfma)):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous() or t.numel() < need[name]:
+            raise ValueError(f"{name}: contiguous int32 device tensor of >= {need[name]} words needed")
+    with torch.cuda.device(windows.device):
+        _check(lib().rlx_build_tables_static(p, rows, windows.data_ptr(), folded.data_ptr(), windows16.data_ptr(),
+                                             mfma.data_ptr(), _stream()), "rlx_build_tables_static")
 
 
 ENGINE_MODES = {"f64": 0, "seed": 1, "skip": 2, "normal": 3, "u48": 4, "sum": 5, "divergent": 6, "f32": 7}

@@ -32,6 +32,17 @@ namespace {
 // reject a record (read and cleared by rlx_check_errors).
 __device__ uint32_t g_err_word;
 
+// Staging of rlx_build_tables_static (the C_i words, then their balanced
+// digits; see k_tab_mf_c), one copy per device for the life of the process.
+// Host code never uses this name as an address: it uses the device address
+// that hipGetSymbolAddress returns for the current device (scratch_ptr).
+static __device__ __align__(256) uint8_t scratch[RLX_STATIC_SCRATCH_BYTES];
+constexpr size_t SCRATCH_CW_BYTES = (size_t)FOLD_G * MF_BYTES * NW * sizeof(uint32_t);
+static_assert(RLX_MFMA_ROW_WORDS == MF_LEVEL_WORDS, "operand rows as the header states");
+static_assert(SCRATCH_CW_BYTES % 256 == 0, "digit staging stays aligned");
+static_assert(SCRATCH_CW_BYTES + (size_t)FOLD_G * MF_COLS * MF_ROWS == RLX_STATIC_SCRATCH_BYTES,
+              "the static scratch holds the staging of every folded row");
+
 // ---------------------------------------------------------------------------
 // tables
 
@@ -110,14 +121,14 @@ __global__ __launch_bounds__(64) void k_tab_fold(const uint32_t* __restrict__ T,
 }
 
 // Matrix-core operands of a step by 2^g generator steps (rlx_mfma.hpp),
-// g < RLX_FOLD_G, in three launches:
+// g < rows (at most RLX_FOLD_G), in three launches:
 // C_i = A_p^(2^g) 256^i mod m for i < 72, one lane per (g, i): its words go
 // to cw (for the sums of k_tab_mf_k) and its balanced digits to column i of
 // bal[g].
 __global__ __launch_bounds__(64) void k_tab_mf_c(const uint32_t* __restrict__ T, uint32_t* __restrict__ cw,
-                                                 int8_t* __restrict__ bal) {
+                                                 int8_t* __restrict__ bal, int rows) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= FOLD_G * MF_BYTES) return;
+  if (t >= rows * MF_BYTES) return;
   const int g = t / MF_BYTES, i = t % MF_BYTES;
   uint32_t a[NW], pw[NW], r[NW];
   load_words(T + ((size_t)(g >> 2) * TAB_COLS + (1u << (g & 3))) * NW, a);
@@ -142,9 +153,10 @@ __global__ __launch_bounds__(64) void k_tab_mf_c(const uint32_t* __restrict__ T,
 
 // K = 128 sum_i C_i as an exact integer (below 2^590, 19 words), one lane
 // per g: its balanced digits are column MF_BYTES of bal[g].
-__global__ __launch_bounds__(64) void k_tab_mf_k(const uint32_t* __restrict__ cw, int8_t* __restrict__ bal) {
+__global__ __launch_bounds__(64) void k_tab_mf_k(const uint32_t* __restrict__ cw, int8_t* __restrict__ bal,
+                                                 int rows) {
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= FOLD_G) return;
+  if (g >= rows) return;
   uint32_t s[NW + 1];
   for (int k = 0; k <= NW; ++k) s[k] = 0;
   for (int i = 0; i < MF_BYTES; ++i) {
@@ -164,9 +176,10 @@ __global__ __launch_bounds__(64) void k_tab_mf_k(const uint32_t* __restrict__ cw
 // The A operands: lane l of fragment f = 3 mt + ks of level g holds, in its
 // 16 bytes j, the digit of output row 32 mt + (l mod 32) of the input column
 // mf_input_column(l div 32, ks, j), zero for a zero column.
-__global__ __launch_bounds__(64) void k_tab_mf_frag(const int8_t* __restrict__ bal, uint32_t* __restrict__ M) {
+__global__ __launch_bounds__(64) void k_tab_mf_frag(const int8_t* __restrict__ bal, uint32_t* __restrict__ M,
+                                                    int rows) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= FOLD_G * MF_FRAGS * 64) return;
+  if (t >= rows * MF_FRAGS * 64) return;
   const int g = t / (MF_FRAGS * 64), f = (t / 64) % MF_FRAGS, l = t % 64;
   const int mt = f / 3, ks = f % 3, h = l / 32, row = 32 * mt + l % 32;
   for (int q = 0; q < 4; ++q) {
@@ -641,9 +654,46 @@ int error_word(hipStream_t, uint32_t** out) {
   return RLX_OK;
 }
 
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept in a fixed table: no
+// allocation, nothing enqueued.
+constexpr int MAX_DEVICES = 64;
+uint8_t* g_scratch[MAX_DEVICES];
+
+int scratch_ptr(uint8_t** out) {
+  int dev;
+  if (current_device(&dev)) return RLX_EHIP;
+  if (dev < 0 || dev >= MAX_DEVICES) return RLX_EINVAL;
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_scratch[dev]) {
+    void* a = nullptr;
+    if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a) return RLX_EHIP;
+    g_scratch[dev] = static_cast<uint8_t*>(a);
+  }
+  *out = g_scratch[dev];
+  return RLX_OK;
+}
+
 bool capturing(hipStream_t s) {
   hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
   return hipStreamIsCapturing(s, &st) != hipSuccess || st != hipStreamCaptureStatusNone;
+}
+
+// The kernels that build the tables of level p on `s`: the 4-bit windows T,
+// the folded multipliers C and matrix-core operands M of the first `rows`
+// step sizes 2^g, and the 16-bit windows W.  cw and bal are the staging of
+// M (FOLD_G * MF_BYTES * NW words and FOLD_G * MF_COLS * MF_ROWS bytes).
+// Enqueues only; allocates and waits for nothing.
+void launch_table_build(uint32_t p, int rows, uint32_t* T, uint32_t* C, uint32_t* W, uint32_t* M, uint32_t* cw,
+                        int8_t* bal, hipStream_t s) {
+  k_tab_base<<<1, 64, 0, s>>>(T, p);
+  const int fill = TAB_ROWS * (TAB_COLS - 2);
+  k_tab_fill<<<(fill + 63) / 64, 64, 0, s>>>(T);
+  k_tab_fold<<<rows, 64, 0, s>>>(T, C);
+  k_tab_win<<<(WIN_ROWS * WIN_COLS + 63) / 64, 64, 0, s>>>(T, W);
+  k_tab_mf_c<<<(rows * MF_BYTES + 63) / 64, 64, 0, s>>>(T, cw, bal, rows);
+  k_tab_mf_k<<<(rows + 63) / 64, 64, 0, s>>>(cw, bal, rows);
+  k_tab_mf_frag<<<rows * MF_FRAGS, 64, 0, s>>>(bal, M, rows);
 }
 
 int tables(uint32_t p, hipStream_t s, Tables* out) {
@@ -684,14 +734,7 @@ int tables(uint32_t p, hipStream_t s, Tables* out) {
     release();
     return RLX_ENOMEM;
   }
-  k_tab_base<<<1, 64, 0, s>>>(t.T, p);
-  const int fill = TAB_ROWS * (TAB_COLS - 2);
-  k_tab_fill<<<(fill + 63) / 64, 64, 0, s>>>(t.T);
-  k_tab_fold<<<FOLD_G, 64, 0, s>>>(t.T, t.C);
-  k_tab_win<<<(WIN_ROWS * WIN_COLS + 63) / 64, 64, 0, s>>>(t.T, t.W);
-  k_tab_mf_c<<<(FOLD_G * MF_BYTES + 63) / 64, 64, 0, s>>>(t.T, cw, bal);
-  k_tab_mf_k<<<(FOLD_G + 63) / 64, 64, 0, s>>>(cw, bal);
-  k_tab_mf_frag<<<FOLD_G * MF_FRAGS, 64, 0, s>>>(bal, t.M);
+  launch_table_build(p, FOLD_G, t.T, t.C, t.W, t.M, cw, bal, s);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
     release();
     return RLX_EHIP;
@@ -860,6 +903,9 @@ const char* rlx_strerror(int code) {
     case RLX_ECAPTURE:
       return "the stream is being captured and this luxury level's tables are not built yet: call "
              "rlx_prepare(p) before capturing";
+    case RLX_ESCRATCH:
+      return "the request needs more staging than the library's static device array holds "
+             "(rlx_build_tables_static: rows <= RLX_FOLD_G)";
     default: return "unknown error";
   }
 }
@@ -895,7 +941,21 @@ int rlx_get_tables(uint32_t p, rlx_engine_tables* out, void* stream) {
   out->folded = t.C;
   out->p = p;
   out->reserved = 0;
+  out->mfma = t.M;
   return RLX_OK;
+}
+
+int rlx_build_tables_static(uint32_t p, uint32_t rows, uint32_t* windows, uint32_t* folded, uint32_t* windows16,
+                            uint32_t* mfma, void* stream) {
+  if (rows > (uint32_t)FOLD_G) return RLX_ESCRATCH;
+  if (rows == 0 || !valid_p(p) || !windows || !folded || !windows16 || !mfma) return RLX_EINVAL;
+  if (!aligned(windows, 4) || !aligned(folded, 4) || !aligned(windows16, 4) || !aligned(mfma, 16)) return RLX_EINVAL;
+  uint8_t* sc;
+  const int rc = scratch_ptr(&sc);
+  if (rc) return rc;
+  launch_table_build(p, (int)rows, windows, folded, windows16, mfma, reinterpret_cast<uint32_t*>(sc),
+                     reinterpret_cast<int8_t*>(sc + SCRATCH_CW_BYTES), as_stream(stream));
+  return launch_status();
 }
 
 int rlx_init_streams(rlx_state* states, uint64_t n, const uint64_t* ids, uint64_t id0, uint32_t p,
