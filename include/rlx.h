@@ -101,7 +101,7 @@ enum {
 /* Message for an error code (static string). */
 const char *rlx_strerror(int code);
 
-/* Library version, e.g. "rlx 0.1 gfx950". */
+/* Library version, e.g. "rlx 0.2 gfx950". */
 const char *rlx_version(void);
 
 /* Build (if needed) the constant tables of luxury level p on the current
@@ -328,7 +328,8 @@ uint32_t rlx_lanes_per_stream(uint64_t n, uint64_t count);
  *                  with the reduction folded into the multiplier.
  * rlx_set_step_kernel applies to all later calls in the process and returns
  * RLX_EINVAL for any other value; rlx_step_kernel reports the current one.
- * The legacy 52-bit doubles and the batch plans always use RLX_STEP_VALU. */
+ * The batch plans (rlx_plan_generate_*) follow the same setting at launch;
+ * the legacy 52-bit doubles always use RLX_STEP_VALU. */
 #define RLX_STEP_MFMA 0
 #define RLX_STEP_VALU 1
 int rlx_set_step_kernel(int kind);

@@ -4,7 +4,8 @@ seg_blocks / lanes) of a Plan by timing the batched launch on the GPU.
 
 Every candidate produces bit-identical values (the tests check this), so the
 choice only affects speed.  Results are cached in a JSON file keyed by the
-device name and a coarse signature of the workload (number of requests,
+device (architecture name and compute-unit count), the library version and
+step kernel, and a coarse signature of the workload (number of requests,
 total values and the luxury levels present, each rounded to a power of two),
 so a serving loop or a benchmark tunes once per shape.
 """
@@ -18,9 +19,9 @@ import time
 import numpy as np
 import torch
 
-from . import Plan
+from . import Plan, lib, step_kernel
 
-DEFAULT_LANES = (8, 16, 32, 64)
+DEFAULT_LANES = (1, 2, 4, 8, 16, 32, 64)
 DEFAULT_SEG_BLOCKS = (512, 1024, 2048, 4096, 8192)
 
 
@@ -37,6 +38,15 @@ def signature(requests) -> str:
     def p2(v):
         return 0 if v <= 0 else int(round(math.log2(v)))
     return f"n2^{p2(n)}-v2^{p2(total)}-p{'.'.join(map(str, levels))}"
+
+
+def device_key(device) -> str:
+    """Cache key of the device and library: architecture name and compute
+    units (the marketing name is generic on this stack), the library version
+    and the step kernel the plans will use."""
+    pr = torch.cuda.get_device_properties(device)
+    arch = getattr(pr, "gcnArchName", "") or torch.cuda.get_device_name(device)
+    return f"{arch}|cu{pr.multi_processor_count}|{lib().rlx_version().decode()}|step{step_kernel()}"
 
 
 def _load() -> dict:
@@ -79,8 +89,7 @@ def tune(requests, states: torch.Tensor, out: torch.Tensor, lanes=DEFAULT_LANES,
          seg_blocks=DEFAULT_SEG_BLOCKS, reps: int = 5, use_cache: bool = True) -> dict:
     """Return {"lanes", "seg_blocks", "ms", "table"} for these requests: the
     cached pick for the workload signature, or the fastest candidate."""
-    dev = torch.cuda.get_device_name(states.device)
-    key = f"{dev}|{signature(requests)}"
+    key = f"{device_key(states.device)}|{signature(requests)}"
     doc = _load() if use_cache else {}
     if use_cache and key in doc:
         return dict(doc[key], cached=True)

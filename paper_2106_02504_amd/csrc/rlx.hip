@@ -279,7 +279,7 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
 // (writeback = 0) and the host advances it by a skip launch on the same
 // stream after this kernel.
 template <Out K, bool TRACE, int LGS, bool MF>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_generate(rlx_state* __restrict__ st, uint32_t n,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out::NORMAL ? 3 : 4))) void k_generate(rlx_state* __restrict__ st, uint32_t n,
                                                     uint64_t count, uint64_t* __restrict__ out,
                                                     uint64_t* __restrict__ trace, uint64_t trace_steps,
                                                     const uint32_t* __restrict__ ctabs,
@@ -321,13 +321,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
   // same for the whole wave)
   if (STAGED) skip_windows(x, l, W);
   const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * FOLD_ROW_WORDS;
-  // MF: the step's matrix-core A operands for A^G, this lane's 16 bytes of
-  // each of the nine fragments, held for the whole launch
-  mf_v4i af[MF_FRAGS];
+  // MF: the step's matrix-core A operands for A^G, staged in LDS once per
+  // block (9 KB) and read by every step
+  __shared__ mf_v4i af[MF ? MF_FRAGS * 64 : 1];
   if constexpr (MF) {
-    const mf_v4i* mt = reinterpret_cast<const mf_v4i*>(mtabs + (size_t)lg * MF_LEVEL_WORDS);
-#pragma unroll
-    for (int f = 0; f < MF_FRAGS; ++f) af[f] = mt[f * 64 + (threadIdx.x & 63)];
+    mf_stage_operands(af, mtabs + (size_t)lg * MF_LEVEL_WORDS, threadIdx.x, BLOCK);
+    __syncthreads();
   }
 
   for (uint32_t k = 0;; ++k) {
@@ -361,7 +360,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void
     }
     if (__any(live && t + (1u << lg) <= nadv)) {
       if constexpr (MF) {
-        mfma_step(x, af, force);
+        mfma_step(x, MfFromArray{af, threadIdx.x & 63}, force);
       } else {
         step(x, constant_table(ctab), force, SgprBarrier());
       }
@@ -594,11 +593,10 @@ __global__ __launch_bounds__(BLOCK) void k_test_step(const uint64_t* __restrict_
     set_one(x);
   }
   if constexpr (MF) {
-    mf_v4i af[MF_FRAGS];
-    const mf_v4i* mt = reinterpret_cast<const mf_v4i*>(mtab);
-#pragma unroll
-    for (int f = 0; f < MF_FRAGS; ++f) af[f] = mt[f * 64 + (threadIdx.x & 63)];
-    mfma_step(x, af, general != 0);
+    __shared__ mf_v4i af[MF_FRAGS * 64];
+    mf_stage_operands(af, mtab, threadIdx.x, BLOCK);
+    __syncthreads();
+    mfma_step(x, MfFromArray{af, threadIdx.x & 63}, general != 0);
   } else {
     step(x, constant_table(ctab), general != 0, SgprBarrier());
   }
@@ -764,22 +762,27 @@ std::atomic<uint32_t> g_lanes_override{0};
 std::atomic<int> g_step_kind{RLX_STEP_MFMA};
 
 // Lanes per record: the largest power of two G <= RLX_MAX_LANES such that
-// the launch stays within sixteen waves per SIMD (2^20 lanes on 256 CUs) and
-// every lane still takes at least 16 generator steps -- or, while the launch
-// has fewer lanes than one wave per SIMD (2^16), at least one step.  A lane
-// pays one windowed multiplication per non-zero 16-bit digit of its index
-// at start-up, so G trades start-up work against parallelism and against the
-// length of the contiguous runs each store instruction writes (16 G bytes
-// per record).  On the many-streams shape G = 16 measured fastest; a single
+// the launch stays within `target` lanes and every lane still takes at least
+// `min_steps` generator steps -- or, while the launch has fewer lanes than
+// one wave per SIMD (2^16), at least one step.  A lane pays one windowed
+// multiplication per non-zero 16-bit digit of its index at start-up, so G
+// trades start-up work against parallelism and against the length of the
+// contiguous runs each store instruction writes (16 G bytes per record).
+// With the matrix-core step (a cheaper step, so start-up weighs more, but
+// waves that each take half as long and leave a shorter tail) the limits
+// are 2^21 lanes and 8 steps, which picks G = 32 on the many-streams shape
+// (65 536 x 4096: 0.372 ms against 0.411 at G = 16 and 0.427 at G = 64);
+// with the vector-ALU step, 2^20 lanes and 16 steps, G = 16 there.  A single
 // stream of 2^20 values ran in 32 us at G = 65536 against 68 us at 4096.
-uint32_t auto_lanes(uint64_t n, uint64_t count) {
+uint32_t auto_lanes(uint64_t n, uint64_t count, bool mf) {
   const uint64_t steps = count / FIELDS + 1;
-  const uint64_t target = 1ull << 20, sparse = 1ull << 16;
+  const uint64_t target = mf ? 1ull << 21 : 1ull << 20, sparse = 1ull << 16;
+  const uint64_t min_steps = mf ? 8 : 16;
   uint64_t g = 1;
   for (;;) {
     const uint64_t g2 = g * 2;
     if (g2 > RLX_MAX_LANES || n > target / g2 || steps / g2 == 0) break;
-    if (steps / g2 < 16 && n > sparse / g2) break;
+    if (steps / g2 < min_steps && n > sparse / g2) break;
     g = g2;
   }
   return (uint32_t)g;
@@ -787,7 +790,7 @@ uint32_t auto_lanes(uint64_t n, uint64_t count) {
 
 uint32_t lanes_for(uint64_t n, uint64_t count) {
   const uint32_t o = g_lanes_override.load(std::memory_order_relaxed);
-  return o ? o : auto_lanes(n, count);
+  return o ? o : auto_lanes(n, count, g_step_kind.load(std::memory_order_relaxed) == RLX_STEP_MFMA);
 }
 
 // Argument checks shared by the generate calls; on success *lg is log2 of
@@ -910,7 +913,7 @@ const char* rlx_strerror(int code) {
   }
 }
 
-const char* rlx_version(void) { return "rlx 0.1 gfx950"; }
+const char* rlx_version(void) { return "rlx 0.2 gfx950"; }
 
 void rlx_constants(uint32_t m_words[18], uint32_t a_words[18]) {
   static const uint32_t a[18] = {0x00000001u, 0, 0, 0, 0, 0, 0x01000000u, 0xFFFF0000u,

@@ -29,6 +29,7 @@
 #include "rlx_arith.hpp"
 #include "rlx_device.hpp"
 #include "rlx_internal.hpp"
+#include "rlx_mfma.hpp"
 
 using namespace rlx;
 using namespace rlx::host;
@@ -69,16 +70,20 @@ struct Header {
   uint32_t pad[2];
   const uint32_t* C[MAX_LEVELS];  // folded multipliers A^(2^g) of each level
   const uint32_t* W[MAX_LEVELS];  // 16-bit window tables A^(j 65536^i) of each level
+  const uint32_t* M[MAX_LEVELS];  // matrix-core step operands of each level
   uint32_t p[MAX_LEVELS];
 };
 
-template <Out K, int LGS>
-__global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ st,
+template <Out K, int LGS, bool MF>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MF ? 3 : 4))) void k_batch(const rlx_state* __restrict__ st,
                                                  const Segment* __restrict__ segs,
                                                  const Item* __restrict__ items, Header* __restrict__ hdr,
                                                  uint64_t* __restrict__ out, uint32_t* __restrict__ err) {
   constexpr uint32_t G = 1u << LGS;
+  constexpr uint32_t NO_SLOT = 0xFFFFFFFFu;
   __shared__ __align__(16) uint64_t stage[BLOCK * SLOT_VALUES];
+  __shared__ mf_v4i af_lds[MF ? MF_FRAGS * 64 : 1];
+  __shared__ uint32_t wave_slot[BLOCK / WAVE];
   const uint32_t tid_blk = threadIdx.x;
   const uint32_t lane = tid_blk & (WAVE - 1);
   const uint32_t team = lane >> LGS;
@@ -86,8 +91,31 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ s
   const uint32_t n_items = __builtin_amdgcn_readfirstlane(hdr->n_items);
   {
     // wave w of the grid runs item w; the grid covers the plan's capacity,
-    // so waves past the current item count exit at once
+    // so waves past the current item count exit at once (after the block's
+    // set-up below)
     const uint32_t it = __builtin_amdgcn_readfirstlane(blockIdx.x * (BLOCK / WAVE) + tid_blk / WAVE);
+    // MF: when every item of the block has the same level (items are laid
+    // out level by level, so nearly always), the block stages that level's
+    // matrix-core operands for A^G in LDS once; otherwise each wave reads
+    // its own level's operands from the table at every step
+    bool lds_ok = false;
+    if constexpr (MF) {
+      if (lane == 0) wave_slot[tid_blk / WAVE] = it < n_items ? items[it].slot : NO_SLOT;
+      __syncthreads();
+      uint32_t s0 = NO_SLOT;
+      bool same = true;
+#pragma unroll
+      for (uint32_t w = 0; w < BLOCK / WAVE; ++w) {
+        const uint32_t v = __builtin_amdgcn_readfirstlane(wave_slot[w]);
+        if (v != NO_SLOT) {
+          same = same && (s0 == NO_SLOT || v == s0);
+          s0 = s0 == NO_SLOT ? v : s0;
+        }
+      }
+      lds_ok = same && s0 != NO_SLOT;
+      if (lds_ok) mf_stage_operands(af_lds, hdr->M[s0] + (size_t)LGS * MF_LEVEL_WORDS, tid_blk, BLOCK);
+      __syncthreads();
+    }
     if (it >= n_items) return;
     const Item item = items[it];
     const uint32_t slot = __builtin_amdgcn_readfirstlane(item.slot);
@@ -135,14 +163,32 @@ __global__ __launch_bounds__(BLOCK) void k_batch(const rlx_state* __restrict__ s
       span = hi > lo ? (uint32_t)(hi - lo) : 0u;
       rel = (int32_t)(sg.jbase - lo);
     }
-    for (uint32_t k = 0;; ++k) {
-      const uint32_t t = l + (k << LGS);
-      const bool live = active && t < nblocks;
-      if (!__any(live)) break;
-      convert_to_lds<K>(x, stage + (size_t)tid_blk * SLOT_VALUES, false);
-      const int32_t u0 = rel + (int32_t)(FIELDS * (t - l));
-      group_store<LGS>(stage, tid_blk, l, u0, span, active, base);
-      if (__any(live && t + G < nblocks)) step(x, constant_table(ctab), false, SgprBarrier());
+    // the loop, once per way of fetching the step's operands
+    auto run = [&](const auto& fetch) {
+      for (uint32_t k = 0;; ++k) {
+        const uint32_t t = l + (k << LGS);
+        const bool live = active && t < nblocks;
+        if (!__any(live)) break;
+        convert_to_lds<K>(x, stage + (size_t)tid_blk * SLOT_VALUES, false);
+        const int32_t u0 = rel + (int32_t)(FIELDS * (t - l));
+        group_store<LGS>(stage, tid_blk, l, u0, span, active, base);
+        if (__any(live && t + G < nblocks)) {
+          if constexpr (MF) {
+            mfma_step(x, fetch, false);
+          } else {
+            step(x, constant_table(ctab), false, SgprBarrier());
+          }
+        }
+      }
+    };
+    if constexpr (MF) {
+      if (lds_ok) {
+        run(MfFromArray{af_lds, lane});
+      } else {
+        run(MfFromBuffer(hdr->M[slot] + (size_t)LGS * MF_LEVEL_WORDS, lane));
+      }
+    } else {
+      run(0);
     }
   }
 }
@@ -277,6 +323,7 @@ int upload(rlx_plan* plan, const Planned& pl, hipStream_t s) {
     if (rc) return rc;
     hd.C[k] = t.C;
     hd.W[k] = t.W;
+    hd.M[k] = t.M;
     hd.p[k] = pl.ps[k];
   }
   // the previous upload must have left the staging buffers
@@ -334,10 +381,16 @@ int plan_launch(rlx_plan* plan, const rlx_state* states, void* out, void* stream
   const uint64_t blocks = (plan->cap + (BLOCK / WAVE) - 1) / (BLOCK / WAVE);
   if (blocks == 0 || blocks > 0x7FFFFFFFull) return RLX_EINVAL;
   uint64_t* o = reinterpret_cast<uint64_t*>(out);
+  const bool mf = rlx_step_kernel() == RLX_STEP_MFMA;
 #define RLX_BATCH(L)                                                                                      \
   case L:                                                                                                 \
-    k_batch<K, L><<<(unsigned)blocks, BLOCK, 0, s>>>(states, plan->d_segs, plan->d_items, plan->d_hdr, o, \
-                                                       err);                                              \
+    if (mf) {                                                                                             \
+      k_batch<K, L, true><<<(unsigned)blocks, BLOCK, 0, s>>>(states, plan->d_segs, plan->d_items, plan->d_hdr, \
+                                                              o, err);                                    \
+    } else {                                                                                              \
+      k_batch<K, L, false><<<(unsigned)blocks, BLOCK, 0, s>>>(states, plan->d_segs, plan->d_items,       \
+                                                               plan->d_hdr, o, err);                      \
+    }                                                                                                     \
     break;
   switch (plan->lg) {
     RLX_BATCH(0) RLX_BATCH(1) RLX_BATCH(2) RLX_BATCH(3) RLX_BATCH(4) RLX_BATCH(5) RLX_BATCH(6)

@@ -307,30 +307,34 @@ __device__ __forceinline__ void group_store(const uint64_t* __restrict__ stage, 
   const uintptr_t a = reinterpret_cast<uintptr_t>(gdst);
   const bool whole = u0 >= 0 && (uint64_t)u0 + FIELDS * gs <= span;
   if (gs >= 8 && __all(active && whole && (a & 127) == 0)) {
-    // the common case of a whole wave on line boundaries, as one branch
-    const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(grp);
+    // the common case of a whole wave on line boundaries, as one branch: one
+    // base address per lane, the six pairs at constant offsets from it
+    const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(grp) + ls;
+    uint64_t* const dst = gdst + 2 * ls;
 #pragma unroll
-    for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<true>(gdst + 2 * (q * gs + ls), g2[q * gs + ls]);
+    for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<true>(dst + 2 * q * gs, g2[q * gs]);
   } else if (active) {
     if (whole) {
       if ((a & 15) == 0) {
-        const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(grp);
+        const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(grp) + ls;
+        uint64_t* const dst = gdst + 2 * ls;
         if (gs >= 8 && (a & 127) == 0) {
 #pragma unroll
-          for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<true>(gdst + 2 * (q * gs + ls), g2[q * gs + ls]);
+          for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<true>(dst + 2 * q * gs, g2[q * gs]);
         } else {
 #pragma unroll
-          for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<false>(gdst + 2 * (q * gs + ls), g2[q * gs + ls]);
+          for (uint32_t q = 0; q < FIELDS / 2; ++q) store_pair<false>(dst + 2 * q * gs, g2[q * gs]);
         }
       } else {
         // pairs k = (values 2k + 1, 2k + 2), k < 6 gs - 1, at 16-byte
         // aligned gdst + 2k + 1
         if (ls == 0) gdst[0] = grp[0];
+        uint64_t* const dst = gdst + 2 * ls + 1;
+        const uint64_t* const src = grp + 2 * ls + 1;
 #pragma unroll
         for (uint32_t q = 0; q < FIELDS / 2; ++q) {
-          const uint32_t k = q * gs + ls;
           if (q + 1 < FIELDS / 2 || ls + 1 < gs) {
-            store_pair<false>(gdst + 2 * k + 1, make_ulonglong2(grp[2 * k + 1], grp[2 * k + 2]));
+            store_pair<false>(dst + 2 * q * gs, make_ulonglong2(src[2 * q * gs], src[2 * q * gs + 1]));
           } else {
             gdst[FIELDS * gs - 1] = grp[FIELDS * gs - 1];
           }

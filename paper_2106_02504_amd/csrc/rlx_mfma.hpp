@@ -122,11 +122,46 @@ __device__ __forceinline__ int64_t mf_word(const mf_v16i& s, int q, int32_t k1, 
   return w;
 }
 
-// X <- A X mod m with the A operands of the launch's multiplier in `af`
-// (af[3 mt + ks]: output-row tile mt, input step ks; this lane's 16 bytes).
-// Must run with all 64 lanes of the wave active.  Returns the canonical
-// residue; `force_general` sends the fold through its general branch.
-__device__ __forceinline__ void mfma_step(uint32_t (&x)[NW], const mf_v4i (&af)[MF_FRAGS], bool force_general) {
+// Copy a step's A operands (MF_FRAGS x 64 lanes x 16 bytes) from global
+// memory into the block's LDS array `dst`; all `nthreads` threads of the
+// block call it, then synchronise before the first step.
+__device__ __forceinline__ void mf_stage_operands(mf_v4i* __restrict__ dst, const uint32_t* __restrict__ src,
+                                                  uint32_t tid, uint32_t nthreads) {
+  const mf_v4i* s = reinterpret_cast<const mf_v4i*>(src);
+  for (uint32_t k = tid; k < (uint32_t)MF_FRAGS * 64; k += nthreads) dst[k] = s[k];
+}
+
+// X <- A X mod m with the A operands of the launch's multiplier delivered by
+// `fetch(3 mt + ks)` (output-row tile mt, input step ks: this lane's 16
+// bytes; read just before its two MFMAs, from LDS or global memory).  Must
+// run with all 64 lanes of the wave active.  Returns the
+// canonical residue; `force_general` sends the fold through its general
+// branch.
+// Operand fetch from an array af[64 f + lane] (LDS, or any memory).
+struct MfFromArray {
+  const mf_v4i* __restrict__ af;
+  uint32_t lane;
+  __device__ __forceinline__ mf_v4i operator()(int f) const { return af[64 * f + lane]; }
+};
+
+// Operand fetch from global memory through a buffer resource: the
+// wave-uniform table address lives in scalar registers and each fetch is one
+// buffer load at this lane's 32-bit offset (no 64-bit address per lane).
+// dword 3 of the resource is the raw-buffer format word of gfx9 parts.
+struct MfFromBuffer {
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t off;  // 16 * lane
+  __device__ __forceinline__ MfFromBuffer(const uint32_t* table, uint32_t lane)
+      : rsrc(__builtin_amdgcn_make_buffer_rsrc(const_cast<uint32_t*>(table), (short)0,
+                                               (int)(MF_LEVEL_WORDS * sizeof(uint32_t)), 0x00020000)),
+        off(16u * lane) {}
+  __device__ __forceinline__ mf_v4i operator()(int f) const {
+    return __builtin_bit_cast(mf_v4i, __builtin_amdgcn_raw_buffer_load_b128(rsrc, (int)off, 1024 * f, 0));
+  }
+};
+
+template <class Fetch>
+__device__ __forceinline__ void mfma_step(uint32_t (&x)[NW], const Fetch& fetch, bool force_general) {
   // signed input digits, halves exchanged across the two lane halves
   uint32_t a[9], b[9];
 #pragma unroll
@@ -147,12 +182,13 @@ __device__ __forceinline__ void mfma_step(uint32_t (&x)[NW], const mf_v4i (&af)[
   uint32_t h = 0;     // word 18
 #pragma unroll
   for (int mt = 0; mt < 3; ++mt) {
-    mf_v16i s0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[3 * mt], b0[0], zero, 0, 0, 0);
-    mf_v16i s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[3 * mt], b1[0], zero, 0, 0, 0);
-    s0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[3 * mt + 1], b0[1], s0, 0, 0, 0);
-    s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[3 * mt + 1], b1[1], s1, 0, 0, 0);
-    s0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[3 * mt + 2], b0[2], s0, 0, 0, 0);
-    s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[3 * mt + 2], b1[2], s1, 0, 0, 0);
+    const mf_v4i f0 = fetch(3 * mt), f1 = fetch(3 * mt + 1), f2 = fetch(3 * mt + 2);
+    mf_v16i s0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, b0[0], zero, 0, 0, 0);
+    mf_v16i s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, b1[0], zero, 0, 0, 0);
+    s0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, b0[1], s0, 0, 0, 0);
+    s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, b1[1], s1, 0, 0, 0);
+    s0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, b0[2], s0, 0, 0, 0);
+    s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, b1[2], s1, 0, 0, 0);
     // rows 64 + 8q + ... of the last tile are zero from q = 2 on (the
     // digits end at row 75)
     const int nq = mt < 2 ? 4 : 2;

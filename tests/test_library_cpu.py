@@ -97,25 +97,36 @@ def test_other_widths_argument_checks(rlx):
 
 def test_automatic_lanes_per_stream(rlx):
     # host-only pick of lanes per record: powers of two within the launch
-    # and step limits; more lanes for few streams, whole waves otherwise
+    # and step limits; more lanes for few streams, whole waves otherwise.
+    # The limits depend on the step kernel: 2^21 lanes and 8 steps per lane
+    # with the matrix-core step, 2^20 and 16 with the vector-ALU step.
     lib = rlx.lib()
     pick = rlx.lanes_per_stream
-    assert pick(65536, 4096) == 16            # the many-streams shape
-    assert pick(1, 1 << 20) == 65536          # one long stream fills the chip
-    assert pick(64, 1 << 20) == 4096          # 16 steps per lane once past 2^16 lanes
-    assert pick(1 << 20, 4096) == 1
-    assert pick(1, 11) == 1 and pick(1, 12) == 2
-    for n in (1, 3, 100, 5000, 1 << 16, 1 << 21):
-        for count in (1, 12, 1000, 1 << 16, 1 << 22):
-            g = pick(n, count)
-            steps = count // 12 + 1
-            assert g & (g - 1) == 0 and 1 <= g <= 65536
-            assert g == 1 or (n * g <= 1 << 20 and steps // g >= 1)
-            assert g == 1 or steps // g >= 16 or n * g <= 1 << 16
-    # the override: powers of two up to 65536, 0 restores the automatic pick
-    assert lib.rlx_set_lanes_per_stream(65536) == 0 and pick(65536, 4096) == 65536
-    assert lib.rlx_set_lanes_per_stream(131072) == 1 and lib.rlx_set_lanes_per_stream(48) == 1
-    assert lib.rlx_set_lanes_per_stream(0) == 0 and pick(65536, 4096) == 16
+    try:
+        for kind, target, min_steps, many in ((rlx.STEP_MFMA, 1 << 21, 8, 32), (rlx.STEP_VALU, 1 << 20, 16, 16)):
+            assert lib.rlx_set_step_kernel(kind) == 0
+            assert pick(65536, 4096) == many          # the many-streams shape
+            assert pick(1, 1 << 20) == 65536          # one long stream fills the chip
+            assert pick(1 << 21, 4096) == 1
+            assert pick(1, 11) == 1 and pick(1, 12) == 2
+            for n in (1, 3, 64, 100, 5000, 1 << 16, 1 << 21):
+                for count in (1, 12, 1000, 1 << 16, 1 << 20, 1 << 22):
+                    g = pick(n, count)
+                    steps = count // 12 + 1
+                    assert g & (g - 1) == 0 and 1 <= g <= 65536
+                    assert g == 1 or (n * g <= target and steps // g >= 1)
+                    assert g == 1 or steps // g >= min_steps or n * g <= 1 << 16
+                    # the largest such power of two
+                    g2 = 2 * g
+                    assert (g2 > 65536 or n * g2 > target or steps // g2 == 0
+                            or (steps // g2 < min_steps and n * g2 > 1 << 16))
+        # the override: powers of two up to 65536, 0 restores the automatic pick
+        assert lib.rlx_set_lanes_per_stream(65536) == 0 and pick(65536, 4096) == 65536
+        assert lib.rlx_set_lanes_per_stream(131072) == 1 and lib.rlx_set_lanes_per_stream(48) == 1
+        assert lib.rlx_set_lanes_per_stream(0) == 0 and pick(65536, 4096) == 16
+    finally:
+        lib.rlx_set_step_kernel(rlx.STEP_MFMA)
+        lib.rlx_set_lanes_per_stream(0)
 
 
 def test_ranlux_form_argument_checks(rlx):
