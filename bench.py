@@ -7,9 +7,20 @@ exponentiation, then draw 4096 float64 uniforms per stream (2^28 doubles,
 2 GiB) into a stream-major [65536, 4096] array in HBM.  The value reported is
 doubles/s over whole steps.
 
-Other legs (reported beside the headline in the same JSON line):
+Order of the GPU work:
+  cold       the headline step from a cold start (W untimed, K timed steps,
+             the first GPU work of the process): the chip's power management
+             boosts, cuts the clock hard and recovers over the first ~50 ms of
+             this load, and these steps fall in that swing
+  legs       the other measurements below, each its own timed region
+  headline   W untimed warm-up steps, then exactly K timed steps, at the
+             clock the chip settles to under this load (`value`, `roofline`)
+
+Legs (reported beside the headline in the same JSON line):
   ceilings   a plain 2 GiB device fill and a 1 GiB copy: the write and copy
              rates this GPU reaches, beside the published 8 TB/s
+  rates      instruction-rate microbenchmarks (vector multiply-adds, carries,
+             float64 adds, int8 matrix-core ops) against the chip's capacity
   u64        the same step writing the 48-bit integers instead of doubles
   f32        the same streams writing float32, one RANLUX number each
              (8192 per stream: the same 2 GiB), checked against the doubles
@@ -18,13 +29,16 @@ Other legs (reported beside the headline in the same JSON line):
   single     one stream (id 1), 2^20 doubles plus the state after each step
   skip       2^20 seeded states, each skipped by a log-uniform offset in
              [1, 2^64) generator steps
+  step_valu  the headline step with the vector-ALU generator step instead of
+             the matrix-core one (same values)
+  batch      8192 requests in one fused launch replayed from a HIP graph
+  serve      the request loop: capacity, then Poisson loads relative to it
   cpu_baseline  the CPU oracle (Python integers) on a bounded sample of the
              many-streams workload, on a process pool; its values are also
              compared bit for bit with the GPU's output of the same streams.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-(defaults K = 200, W = 100: the warm-up lets the chip's power management
-settle, so the timed steps measure the sustained rate)
+(defaults K = 200, W = 100)
 """
 from __future__ import annotations
 
@@ -43,10 +57,15 @@ P = 2048
 N_STREAMS = 65536
 DRAWS = 4096
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, published
-VALU_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes x 2.4 GHz (full-rate 32-bit ops)
-MADS_PER_DOUBLE = 27              # 18 x 18 32-bit multiply-adds per step / 12 doubles
+SIMDS = 256 * 4                   # 256 CUs x 4 SIMDs
+CLOCK_HZ = 2.4e9                  # peak engine clock
+VALU_WAVE_ISSUE = SIMDS * CLOCK_HZ / 4   # wave64 vector instructions per second (4 cycles each)
+INT8_PEAK_OPS = 5.0e15            # dense int8 matrix-core peak, published
+MFMA_OPS = 2 * 32 * 32 * 32       # operations of one v_mfma_i32_32x32x32_i8
+MATRIX_OPS_PER_DOUBLE = 2 * 73 * 73 / 12   # a step's contraction: 72 input bytes + the constant
+                                           # column by 73 output digits, per 12 doubles
 KERNEL_SOURCES = ("paper_2106_02504_amd/csrc/rlx.hip", "include/rlx_arith.hpp",
-                  "paper_2106_02504_amd/csrc/rlx_device.hpp")
+                  "paper_2106_02504_amd/csrc/rlx_device.hpp", "paper_2106_02504_amd/csrc/rlx_mfma.hpp")
 
 
 # ---------------------------------------------------------------------------
@@ -92,7 +111,9 @@ def serve_sample(n_requests: int, k=16, width=512):
     for ties), and the leg serves the same request list (the same stream ids
     and counts) five times after a warm-up: three Poisson loads, the timed
     capacity run and an untimed check run with every request arriving at
-    once, so every start is known in advance from the counts alone."""
+    once, so every start is known in advance from the counts alone (the
+    order of the middle runs -- capacity first, then the Poisson loads --
+    does not change any cursor at the check run)."""
     import random
     import workloads
     warm = workloads.serve_requests(64, 1.0, seed=6)
@@ -169,9 +190,69 @@ def measured_counters(kernel: str) -> dict:
     return ent
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per launch from the committed counter summary, or None."""
-    return measured_counters(kernel).get("hbm_bytes_per_launch")
+def kernel_record(kind: int) -> str:
+    """Name of the headline kernel's entry in profiles/traffic.json."""
+    return "k_generate_f64_many_streams_" + ("mfma" if kind == 0 else "valu")
+
+
+def compute_side(counters: dict, gen_ms: float, total: int, kind: int) -> dict:
+    """The headline kernel against the compute units, from the committed
+    counter run on the current sources (rocprofv3 SQ_INSTS_VALU,
+    SQ_INSTS_MFMA): vector instructions issued against the issue capacity of
+    1024 SIMDs at 2.4 GHz in the measured kernel time, and int8 matrix-core
+    operations against the published dense peak, both executed and
+    algorithmic (72 bytes + the constant column by 73 output digits per
+    step, 12 doubles per step)."""
+    out = {"note": "executed instructions per launch from profiles/traffic.json (same kernel sources); "
+                   "null when those counters were taken on other sources"}
+    valu = counters.get("valu_insts_per_launch")
+    mfma = counters.get("mfma_insts_per_launch")
+    sec = gen_ms * 1e-3
+    out["valu"] = None if not valu else {
+        "insts_per_launch": valu, "frac_of_issue_at_2.4GHz": round(valu / (VALU_WAVE_ISSUE * sec), 4)}
+    if kind == 0:
+        algo = MATRIX_OPS_PER_DOUBLE * total / sec
+        out["matrix_int8"] = {"algorithmic_ops_per_s": algo, "algorithmic_frac": round(algo / INT8_PEAK_OPS, 4),
+                              "peak_ops_per_s": INT8_PEAK_OPS}
+        if mfma:
+            ex = mfma * MFMA_OPS / sec
+            out["matrix_int8"].update(executed_ops_per_s=ex, executed_frac=round(ex / INT8_PEAK_OPS, 4),
+                                      mfma_insts_per_launch=mfma)
+    return out
+
+
+def rates_leg(rlx, torch, dev) -> dict:
+    """Issue rates of the instruction kinds the kernels use (rlx_test_rates:
+    independent chains, 8 waves per SIMD), against the chip's capacity at
+    2.4 GHz: wave64 vector instructions per 4 cycles per SIMD, and the
+    published dense int8 matrix-core peak."""
+    n_threads = SIMDS * 8 * 64
+    res = {"waves_per_simd": 8}
+    for kind, (name, per_iter) in rlx.RATE_KINDS.items():
+        iters = 1024 if kind == 3 else 4096
+        out = torch.empty(n_threads, dtype=torch.int32, device=dev)
+        for _ in range(2):
+            rlx.test_rates(kind, iters, n_threads, out)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            rlx.test_rates(kind, iters, n_threads, out)
+            e1.record()
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1) * 1e-3)
+        t = sorted(times)[len(times) // 2]
+        wave_insts = n_threads / 64 * per_iter * iters
+        ent = {"insts_per_iteration": per_iter, "seconds": t, "wave_insts_per_s": wave_insts / t}
+        if kind == 3:
+            ent["ops_per_s"] = wave_insts * MFMA_OPS / t
+            ent["frac_of_int8_peak"] = round(ent["ops_per_s"] / INT8_PEAK_OPS, 4)
+        else:
+            ent["frac_of_issue_at_2.4GHz"] = round(wave_insts / t / VALU_WAVE_ISSUE, 4)
+        res[name] = ent
+    return res
 
 
 SETTLE_STEPS = 100   # steps of this load after which the chip's clock has settled
@@ -223,9 +304,9 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
     else:
         tuned = autotune.tune(req, st, out)
     plan = rlx.Plan(req, lanes=tuned["lanes"], seg_blocks=tuned["seg_blocks"], device=dev)
-    reps = max(5, args.steps // 2)
-    ms = autotune.time_plan(plan, st, out, reps)
-    # the same launch replayed from a HIP graph
+    # the same launch captured in a HIP graph (the form a serving or training
+    # loop replays); direct launches and replays are timed alternately, one
+    # at a time with HIP events, and the medians reported
     s = torch.cuda.Stream(device=dev)
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -237,14 +318,19 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
         plan.generate_f64(st, out)
     g.replay()
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
+    reps = max(20, args.steps // 4)
+    direct, replay = [], []
     for _ in range(reps):
-        g.replay()
-    e1.record()
-    e1.synchronize()
-    gms = e0.elapsed_time(e1) / reps
+        for fn, acc in ((lambda: plan.generate_f64(st, out), direct), (g.replay, replay)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            acc.append(e0.elapsed_time(e1))
+    ms = float(np.median(direct))
+    gms = float(np.median(replay))
     exact = None
     if checks is not None:
         exact = True
@@ -255,8 +341,9 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
                 exact &= got.view(np.uint64).tolist() == vals
     info = plan.info()
     plan.close()
-    return {"value": total / (ms * 1e-3), "unit": "doubles/s", "ms_per_launch": ms,
-            "graph_replay_ms": gms, "graph_value": total / (gms * 1e-3),
+    return {"value": total / (gms * 1e-3), "unit": "doubles/s", "graph_replay_ms": gms,
+            "direct_ms": ms, "direct_value": total / (ms * 1e-3), "reps": reps,
+            "timing": "value from HIP-graph replays; direct launches and replays alternate, medians of each",
             "lanes_per_segment": tuned["lanes"], "seg_blocks": tuned["seg_blocks"],
             "draws_per_lane": 12 * tuned["seg_blocks"] // tuned["lanes"],
             "autotune": {"cached": tuned.get("cached"), "table": tuned.get("table")},
@@ -266,10 +353,11 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
                         "counts floor(2^(20U)) in [1, 2^20], one fused launch"}
 
 
-def serve_leg(rlx, torch, np, dev, plain_rate, args, checks=None):
+def serve_leg(rlx, torch, np, dev, args, checks=None):
     """Poisson arrivals of requests of log-uniform size 10^3..10^8 from a pool
-    of 10^6 streams (p = 2048), at 0.5, 0.8 and 0.95 of the plain kernel's
-    measured rate divided by the mean request size."""
+    of 10^6 streams (p = 2048).  The server's capacity is measured first (the
+    same requests all arriving at once); the loads are then 0.5, 0.8 and 0.95
+    of that capacity divided by the mean request size."""
     import workloads
     from paper_2106_02504_amd.serve import Server
     mean_n = workloads.mean_serve_size()
@@ -281,19 +369,20 @@ def serve_leg(rlx, torch, np, dev, plain_rate, args, checks=None):
     # warm-up: the first launches load the kernels' code and fill the plans
     warm = workloads.serve_requests(64, 1.0, seed=6)
     srv.run([0.0] * len(warm), [r.stream_id for r in warm], [r.count for r in warm])
+    # capacity: the requests all arriving at once
+    reqs = workloads.serve_requests(args.serve_requests, 1.0)
+    st = srv.run([0.0] * len(reqs), [r.stream_id for r in reqs], [r.count for r in reqs])
+    summ = st.summary()
+    cap = summ["doubles_per_s"]
+    res["capacity"] = {"doubles_per_s": cap, "batches": summ["batches"], "makespan_s": summ["makespan_s"]}
     for frac in (0.5, 0.8, 0.95):
-        lam = frac * plain_rate / mean_n
+        lam = frac * cap / mean_n
         reqs = workloads.serve_requests(args.serve_requests, lam)
         st = srv.run([r.arrival_s for r in reqs], [r.stream_id for r in reqs], [r.count for r in reqs])
         summ = st.summary()
         summ.pop("starts", None)
-        res["runs"].append(dict(load=frac, rate_per_s=lam, **summ))
-    # capacity: the same requests all arriving at once
+        res["runs"].append(dict(load=frac, load_of="measured capacity", rate_per_s=lam, **summ))
     reqs = workloads.serve_requests(args.serve_requests, 1.0)
-    st = srv.run([0.0] * len(reqs), [r.stream_id for r in reqs], [r.count for r in reqs])
-    summ = st.summary()
-    res["capacity"] = {"doubles_per_s": summ["doubles_per_s"], "fraction_of_plain": summ["doubles_per_s"] / plain_rate,
-                       "batches": summ["batches"], "makespan_s": summ["makespan_s"]}
     # check run (untimed: the copies synchronise): the same load again, with
     # sampled requests compared with oracle windows computed in the CPU leg
     if checks is None:
@@ -313,7 +402,7 @@ def serve_leg(rlx, torch, np, dev, plain_rate, args, checks=None):
     exact = all(i in seen and all(got == want for (_, got), (_, want) in zip(seen[i], checks[i]))
                 for i in checks) and all(int(starts[i]) == st0[i] for i in checks)
     res["capacity"].update(bit_exact_sample=exact,
-                           sample=f"check run after the capacity run: first and last 512 values of {len(checks)} "
+                           sample=f"check run after the Poisson runs: first and last 512 values of {len(checks)} "
                                   f"requests against the oracle")
     srv.close()
     return res
@@ -357,15 +446,11 @@ def engine_leg(rlx, torch, dev, args):
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # The chip's power management takes about 50 ms of this load to settle:
-    # the first ~25 launches swing between 0.42 and 0.64 ms, and from about
-    # launch 100 on the kernel holds at one duration (+-1%).  The default
-    # warm-up covers that; the timed steps then measure the sustained rate.
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=SETTLE_STEPS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=16384)
-    ap.add_argument("--legs", default="ceilings,u64,normal,f32,lcg52,single,skip,engine,batch,serve",
+    ap.add_argument("--legs", default="ceilings,rates,u64,normal,f32,lcg52,single,skip,step_valu,engine,batch,serve",
                     help="extra legs to time (comma list or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-lanes", type=int, default=64, help="lanes per segment of the server's plans")
@@ -373,6 +458,8 @@ def main() -> int:
     ap.add_argument("--engine-draws", type=int, default=10 ** 6,
                     help="draws per thread in the device-engine leg (the paper's 10^6)")
     ap.add_argument("--lanes", type=int, default=0, help="force lanes per stream (0 = library's pick)")
+    ap.add_argument("--step-kernel", choices=("mfma", "valu"), default="mfma",
+                    help="generator step of the headline: int8 matrix cores (default) or vector ALU")
     ap.add_argument("--batch-config", default="",
                     help="LANES:SEG_BLOCKS for the batch leg instead of autotuning (e.g. 32:4096)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -411,64 +498,53 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    kind = rlx.STEP_MFMA if args.step_kernel == "mfma" else rlx.STEP_VALU
+    rlx.set_step_kernel(kind)
     rlx.prepare(P)
     rlx.set_lanes_per_stream(args.lanes)
     lanes = rlx.lanes_per_stream(N_STREAMS, DRAWS)
     st = rlx.new_states(N_STREAMS, device=dev)
     out = torch.empty((N_STREAMS, DRAWS), dtype=torch.float64, device=dev)
-
-    ev = []
-    ev_init = []
-
-    def step():
-        i0 = torch.cuda.Event(enable_timing=True)
-        i0.record(stream)
-        rlx.init_streams(st, P, id0=0)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        rlx.generate_f64(st, DRAWS, P, out=out)
-        e1.record(stream)
-        ev.append((e0, e1))
-        ev_init.append((i0, e0))
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev.clear()
-    ev_init.clear()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / args.steps
-    gen_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    init_ms = float(np.mean([a.elapsed_time(b) for a, b in ev_init]))
     total = N_STREAMS * DRAWS
-    value = total / wall
+    bytes_per_launch = total * 8 + N_STREAMS * 80 * 2
 
-    # With fewer than 100 warm-up steps the timed steps above fall inside
-    # the power-management swing of the first ~50 ms of load.  The requested
-    # measurement stays the headline; this one is reported beside it: the
-    # same step after 100 untimed and over 200 timed steps.
-    sustained = None
-    if args.warmup < SETTLE_STEPS:
-        for _ in range(SETTLE_STEPS):
+    def run_steps(warmup: int, steps: int) -> dict:
+        """W untimed then K timed steps (seeding + generation); wall time
+        per step between device synchronisations, and the two kernels' mean
+        durations from HIP events on the launch stream."""
+        ev, ev_init = [], []
+
+        def step():
+            i0 = torch.cuda.Event(enable_timing=True)
+            i0.record(stream)
+            rlx.init_streams(st, P, id0=0)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rlx.generate_f64(st, DRAWS, P, out=out)
+            e1.record(stream)
+            ev.append((e0, e1))
+            ev_init.append((i0, e0))
+
+        for _ in range(warmup):
             step()
         torch.cuda.synchronize()
         ev.clear()
         ev_init.clear()
         t0 = time.perf_counter()
-        for _ in range(200):
+        for _ in range(steps):
             step()
         torch.cuda.synchronize()
-        s_wall = (time.perf_counter() - t0) / 200
-        s_gen = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-        s_bytes = total * 8 + N_STREAMS * 80 * 2
-        sustained = {"value": total / s_wall, "ms_per_step": s_wall * 1e3, "kernel_ms": round(s_gen, 4),
-                     "hbm_frac": round(s_bytes / (s_gen * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "note": f"{SETTLE_STEPS} untimed then 200 timed steps, because --warmup {args.warmup} "
-                             f"< {SETTLE_STEPS}"}
+        wall = (time.perf_counter() - t0) / steps
+        gen = [a.elapsed_time(b) for a, b in ev]
+        return {"value": total / wall, "ms_per_step": wall * 1e3, "kernel_ms": float(np.mean(gen)),
+                "kernel_ms_min": float(np.min(gen)), "kernel_ms_max": float(np.max(gen)),
+                "init_ms": float(np.mean([a.elapsed_time(b) for a, b in ev_init])),
+                "hbm_frac": bytes_per_launch / (float(np.mean(gen)) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+    # cold: the same steps as the headline, as the first GPU work of the
+    # process (inside the power-management swing of the first ~50 ms)
+    cold = run_steps(args.warmup, args.steps)
 
     # bit-exact check of the sampled streams against the oracle's values
     bit_exact = None
@@ -476,35 +552,6 @@ def main() -> int:
         got = (out[: args.cpu_streams] * 2.0 ** 48).to(torch.int64).cpu().numpy().view(np.uint64)
         bit_exact = bool(np.array_equal(got, ref))
         cpu["bit_exact_vs_gpu"] = bit_exact
-
-    # roofline of the generation kernel: output doubles + state read/write
-    bytes_per_launch = total * 8 + N_STREAMS * 80 * 2
-    achieved_gbs = bytes_per_launch / (gen_ms * 1e-3) / 1e9
-    traffic = measured_traffic("k_generate_f64_many_streams")
-    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "k_generate<f64>", "kernel_ms": round(gen_ms, 4),
-                "algorithmic_bytes_per_launch": bytes_per_launch}
-    mads = total * MADS_PER_DOUBLE
-    roofline_alu = {"bound": "alu", "achieved": round(mads / (gen_ms * 1e-3) / 1e12, 2),
-                    "peak": round(VALU_LANE_OPS / 1e12, 2), "unit": "Tmad/s",
-                    "frac": round(mads / (gen_ms * 1e-3) / VALU_LANE_OPS, 4),
-                    "note": "27 32x32->64 multiply-adds per double (schoolbook 18x18 words per 12 doubles) "
-                            "against one full-rate 32-bit VALU op per lane per cycle"}
-
-    # VALU issue: instructions the kernel executes per launch (SQ_INSTS_VALU
-    # from the committed counter run, same workload) against what the SIMDs
-    # can issue in the measured kernel time: one wave64 VALU instruction per
-    # 4 cycles on each of 1024 SIMDs at 2.4 GHz
-    valu_insts = measured_counters("k_generate_f64_many_streams").get("valu_insts_per_launch")
-    valu_issue = None
-    if valu_insts:
-        cap = 1024 * gen_ms * 1e-3 * 2.4e9 / 4
-        valu_issue = {"insts_per_launch": valu_insts, "issue_capacity_at_2.4GHz": round(cap),
-                      "frac": round(valu_insts / cap, 4),
-                      "note": "executed VALU instructions (rocprofv3 SQ_INSTS_VALU, profiles/traffic.json) over "
-                              "the issue capacity of 1024 SIMDs x 2.4 GHz / 4 cycles per wave64 instruction in the "
-                              "measured kernel time; counts executed work, not algorithmic work"}
 
     legs = {}
     if "ceilings" in wanted:
@@ -515,10 +562,11 @@ def main() -> int:
         other = buf[1 << 27:]
         dt_fill = timed(lambda: buf.fill_(0.5), stream, 50, 20, torch)
         dt_copy = timed(lambda: other.copy_(half), stream, 50, 20, torch)
-        fill_gbs = (1 << 31) / dt_fill / 1e9
-        legs["ceilings"] = {"fill_2GiB_gbs": fill_gbs, "copy_1GiB_read_plus_write_gbs": (1 << 31) / dt_copy / 1e9,
-                            "generate_fraction_of_fill": bytes_per_launch / (gen_ms * 1e-3) / 1e9 / fill_gbs}
+        legs["ceilings"] = {"fill_2GiB_gbs": (1 << 31) / dt_fill / 1e9,
+                            "copy_1GiB_read_plus_write_gbs": (1 << 31) / dt_copy / 1e9}
         del buf, half, other
+    if "rates" in wanted:
+        legs["rates"] = rates_leg(rlx, torch, dev)
     if "u64" in wanted:
         outu = torch.empty((N_STREAMS, DRAWS), dtype=torch.int64, device=dev)
 
@@ -546,7 +594,6 @@ def main() -> int:
                           "one_lane_ms": dt1 * 1e3, "one_lane_us_per_generator_step": dt1 * 1e6 / steps1,
                           "workload": "1 stream (id 1), p=2048, 2^20 doubles + state after each step"}
     if "skip" in wanted:
-        import workloads
         n3 = 1 << 20
         st3 = rlx.new_states(n3, device=dev)
         offs = torch.from_numpy(workloads.skip_offsets(n3).view(np.int64)).to(dev)
@@ -558,7 +605,6 @@ def main() -> int:
         legs["skip"] = {"value": n3 / dt, "unit": "states/s", "ms_per_step": dt * 1e3,
                         "workload": "2^20 states, offsets log-uniform in [1, 2^64) steps"}
         del st3, offs
-
     if "normal" in wanted:
         outn = torch.empty((N_STREAMS, DRAWS), dtype=torch.float64, device=dev)
 
@@ -598,15 +644,30 @@ def main() -> int:
                          "multiples_of_2^-52": bool(((out52 * 2.0 ** 52).frac() == 0).all()),
                          "workload": "many-streams shape, legacy raw-LCG doubles (11 per step)"}
         del out52
+    if "step_valu" in wanted:
+        # the headline step with the other generator-step kernel (and its own
+        # lane choice): same values, different instruction mix
+        other = rlx.STEP_VALU if kind == rlx.STEP_MFMA else rlx.STEP_MFMA
+        ref_out = out.clone()
+        rlx.set_step_kernel(other)
+        rlx.set_lanes_per_stream(0)
+        alt = run_steps(max(5, args.warmup // 2), max(5, args.steps // 2))
+        legs["step_valu" if other == rlx.STEP_VALU else "step_mfma"] = dict(
+            alt, unit="doubles/s", lanes_per_stream=rlx.lanes_per_stream(N_STREAMS, DRAWS),
+            same_values=bool(torch.equal(out, ref_out)))
+        del ref_out
+        rlx.set_step_kernel(kind)
+        rlx.set_lanes_per_stream(args.lanes)
     if "engine" in wanted:
         legs["engine"] = engine_leg(rlx, torch, dev, args)
 
     if "batch" in wanted:
         del out
         legs["batch"] = batch_leg(rlx, torch, np, dev, batch_reqs, checks, args)
+        out = torch.empty((N_STREAMS, DRAWS), dtype=torch.float64, device=dev)
 
     if "serve" in wanted:
-        legs["serve"] = serve_leg(rlx, torch, np, dev, value, args, serve_checks)
+        legs["serve"] = serve_leg(rlx, torch, np, dev, args, serve_checks)
 
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
@@ -614,6 +675,35 @@ def main() -> int:
         a.fill_(1.0)
         b.copy_(a)
         torch.cuda.synchronize()
+        del a, b
+
+    # the headline: W untimed warm-up steps, then exactly K timed steps
+    head = run_steps(args.warmup, args.steps)
+    value = head["value"]
+    gen_ms = head["kernel_ms"]
+
+    # rates relative to the headline
+    if "ceilings" in legs:
+        legs["ceilings"]["generate_fraction_of_fill"] = (bytes_per_launch / (gen_ms * 1e-3) / 1e9
+                                                         / legs["ceilings"]["fill_2GiB_gbs"])
+    if "serve" in legs:
+        legs["serve"]["capacity"]["fraction_of_plain"] = legs["serve"]["capacity"]["doubles_per_s"] / value
+    if "batch" in legs:
+        legs["batch"]["fraction_of_plain"] = legs["batch"]["value"] / value
+
+    # roofline of the generation kernel: output doubles + state read/write
+    achieved_gbs = bytes_per_launch / (gen_ms * 1e-3) / 1e9
+    counters = measured_counters(kernel_record(kind))
+    roofline = {"bound": "hbm", "achieved": round(achieved_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved_gbs / HBM_PEAK_GBS, 4), "traffic": counters.get("hbm_bytes_per_launch"),
+                "kernel": f"k_generate<f64> ({args.step_kernel} step, {lanes} lanes per stream)",
+                "kernel_ms": round(gen_ms, 4), "algorithmic_bytes_per_launch": bytes_per_launch,
+                "traffic_note": "HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, each scaled by the "
+                                "same counter on a plain device copy (profiles/traffic.json); null unless those "
+                                "counters were taken on the current kernel sources"}
+    # the compute side: the matrix cores' int8 operations and the vector ALU
+    # issue, from the committed counter run on the same sources
+    compute = compute_side(counters, gen_ms, total, kind)
 
     rec = {
         "metric": "doubles/sec (1 GPU, bit-exact vs oracle), plain vs batched; p99 request latency",
@@ -622,7 +712,7 @@ def main() -> int:
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -631,14 +721,15 @@ def main() -> int:
         "config": {"workload": "many-streams: 65536 streams seeded with ids 0..65535 by skip-ahead "
                                "seeding, p=2048, 4096 float64 per stream (2^28 doubles) stream-major in HBM",
                    "streams": N_STREAMS, "draws_per_stream": DRAWS, "p": P, "output": "float64",
-                   "lanes_per_stream": lanes},
+                   "lanes_per_stream": lanes, "step_kernel": args.step_kernel},
         "bit_exact": bit_exact,
-        "init_ms": round(init_ms, 4),
+        "init_ms": round(head["init_ms"], 4),
         "device": device_info(torch, dev),
         "roofline": roofline,
-        "roofline_alu": roofline_alu,
-        "sustained": sustained,
-        "valu_issue": valu_issue,
+        "compute": compute,
+        "cold": dict(cold, note="the same W + K steps as the first GPU work of the process, before the legs: "
+                                "inside the power-management swing of the first ~50 ms of this load"),
+        "order": "cold, legs, headline: the headline is timed after the legs, at the clock the chip settles to",
         "cpu_baseline": cpu,
         "legs": legs,
         "kernel_sources_sha": sources_sha(),

@@ -471,6 +471,19 @@ int rlx_test_engine(rlx_state *states, uint64_t n, uint64_t count,
 int rlx_test_step(const uint64_t *x, uint64_t *out, uint64_t n, uint32_t p,
                   uint32_t g, int kind, int general, void *stream);
 
+/* Instruction-rate microbenchmark of one unit the kernels use: n_threads
+ * lanes (a multiple of 256) each run `iters` iterations of independent
+ * chains of one instruction kind and write one word to out[i]:
+ *   kind 0  v_mad_u64_u32 (32 x 32 + 64 -> 64 bits), 64 per iteration
+ *   kind 1  add-with-carry chains (v_add_co_u32 / v_addc_co_u32), 80 vector
+ *           instructions per iteration, 64 of them with carry in or out
+ *   kind 2  v_fma_f64, 64 per iteration
+ *   kind 3  v_mfma_i32_32x32x32_i8 (65536 int8 operations each), 18 per
+ *           iteration per wave
+ * Time the launch with events to get the issue rate; the values written are
+ * meaningless. */
+int rlx_test_rates(int kind, uint32_t iters, uint32_t *out, uint64_t n_threads, void *stream);
+
 /* rlx_generate_u64 with every rare-case branch of the step and the
  * conversion taken by all lanes (the exact general code), so that the general
  * code can be compared with the fast path on ordinary inputs. */

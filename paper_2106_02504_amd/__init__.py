@@ -29,7 +29,7 @@ __all__ = [
     "set_lanes_per_stream", "lanes_per_stream", "set_step_kernel", "step_kernel", "STEP_MFMA", "STEP_VALU",
     "skip_values", "export_ranlux", "import_ranlux", "REQUEST_DTYPE", "requests_array", "Plan", "plan_dry_run",
     "constants", "test_mulmod", "test_pow", "test_to_ranlux",
-    "test_generate_u64_general", "test_step", "STATE_WORDS",
+    "test_generate_u64_general", "test_step", "test_rates", "RATE_KINDS", "STATE_WORDS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -79,6 +79,7 @@ _SIGS = {
     "rlx_test_to_ranlux": (_int, [_vp, _vp, _vp, _u64, _vp]),
     "rlx_test_generate_u64_general": (_int, [_vp, _u64, _u64, _vp, _u32, _vp]),
     "rlx_test_step": (_int, [_vp, _vp, _u64, _u32, _u32, _int, _int, _vp]),
+    "rlx_test_rates": (_int, [_int, _u32, _vp, _u64, _vp]),
 }
 
 _lib = None
@@ -571,6 +572,20 @@ def test_step(x: torch.Tensor, p: int, g: int, kind: int = STEP_MFMA, general: b
     with torch.cuda.device(x.device):
         _check(lib().rlx_test_step(x.data_ptr(), out.data_ptr(), n, p, g, kind, int(general), _stream()),
                "rlx_test_step")
+    return out
+
+
+# rlx_test_rates kinds: (name, instructions per iteration per lane, unit)
+RATE_KINDS = {0: ("v_mad_u64_u32", 64), 1: ("add_with_carry_valu", 80), 2: ("v_fma_f64", 64),
+              3: ("v_mfma_i32_32x32x32_i8", 18)}
+
+
+def test_rates(kind: int, iters: int, n_threads: int, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Launch the instruction-rate microbenchmark `kind` (see RATE_KINDS) on
+    the current stream; returns the (meaningless) output words."""
+    if out is None:
+        out = torch.empty(n_threads, dtype=torch.int32, device="cuda")
+    _check(lib().rlx_test_rates(kind, iters, out.data_ptr(), n_threads, _stream()), "rlx_test_rates")
     return out
 
 

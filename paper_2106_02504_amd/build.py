@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRC = [os.path.join(HERE, "csrc", f) for f in ("rlx.hip", "rlx_batch.hip", "rlx_engine_test.hip")]
+SRC = [os.path.join(HERE, "csrc", f) for f in ("rlx.hip", "rlx_batch.hip", "rlx_engine_test.hip", "rlx_rates.hip")]
 LIB = os.path.join(HERE, "librlx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
