@@ -36,6 +36,9 @@ Legs (reported beside the headline in the same JSON line):
   cpu_baseline  the CPU oracle (Python integers) on a bounded sample of the
              many-streams workload, on a process pool; its values are also
              compared bit for bit with the GPU's output of the same streams.
+  cpu_native the C++ CPU baseline (unsigned __int128, one thread per core of
+             the box's share) on the many-streams, single-stream, skip and
+             batch workloads, before any GPU work
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 (defaults K = 200, W = 100)
@@ -157,6 +160,52 @@ def cpu_baseline(n_streams: int, workers: int):
             res[lo:lo + arr.shape[0]] = arr
     dt = time.perf_counter() - t0
     return res, dt
+
+
+def cpu_native_leg(workers: int, ref=None, batch_reqs=None) -> dict:
+    """The C++ CPU baseline (paper_2106_02504_amd.cpu: nine 64-bit words,
+    unsigned __int128 products, `workers` std::threads) on the survey's
+    configurations: C2 in full (65536 streams x 4096 doubles, seeding
+    included), C1 block-split over the threads (one stream, 2^20 doubles),
+    C3 (2^20 states seeded and skipped by log-uniform offsets) and C4 (the
+    8192-request batch).  Run before any GPU work; values of the first C2
+    streams are compared with the oracle's."""
+    import numpy as np
+    import workloads
+    from paper_2106_02504_amd import cpu as rcpu
+    res = {"kind": "native C++ (unsigned __int128, std::thread)", "cores": workers}
+    t0 = time.perf_counter()
+    out = rcpu.generate(N_STREAMS, 0, DRAWS, P, nthreads=workers)
+    dt = time.perf_counter() - t0
+    res["many_streams"] = {"value": N_STREAMS * DRAWS / dt, "unit": "doubles/s", "seconds": dt,
+                           "workload": "65536 streams (ids 0..65535) x 4096 doubles, p=2048, seeding included"}
+    if ref is not None:
+        got = (out[: ref.shape[0]] * 2.0 ** 48).astype(np.uint64)
+        res["many_streams"]["bit_exact_vs_oracle"] = bool(np.array_equal(got, ref))
+    del out
+    t0 = time.perf_counter()
+    rcpu.generate_split(1, 1 << 20, P, nthreads=workers)
+    dt = time.perf_counter() - t0
+    res["single"] = {"value": (1 << 20) / dt, "unit": "doubles/s", "seconds": dt,
+                     "workload": "1 stream (id 1), 2^20 doubles, steps split over the threads by skip"}
+    n3 = 1 << 20
+    t0 = time.perf_counter()
+    x = rcpu.seed(n3, 0, P, nthreads=workers)
+    t1 = time.perf_counter()
+    rcpu.skip(x, workloads.skip_offsets(n3), P, nthreads=workers)
+    t2 = time.perf_counter()
+    res["skip"] = {"value": n3 / (t2 - t1), "unit": "states/s", "seconds": t2 - t1, "seed_seconds": t1 - t0,
+                   "workload": "2^20 states, offsets log-uniform in [1, 2^64) steps"}
+    del x
+    if batch_reqs is not None:
+        t0 = time.perf_counter()
+        out, _ = rcpu.generate_requests([r.stream_id for r in batch_reqs], [0] * len(batch_reqs),
+                                        [r.count for r in batch_reqs], [r.p for r in batch_reqs], nthreads=workers)
+        dt = time.perf_counter() - t0
+        res["batch"] = {"value": out.shape[0] / dt, "unit": "doubles/s", "seconds": dt,
+                        "workload": "8192 requests, own stream each, p over five levels, log-uniform counts"}
+        del out
+    return res
 
 
 # ---------------------------------------------------------------------------
@@ -450,7 +499,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=SETTLE_STEPS)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=16384)
-    ap.add_argument("--legs", default="ceilings,rates,u64,normal,f32,lcg52,single,skip,step_valu,engine,batch,serve",
+    ap.add_argument("--legs",
+                    default="cpu_native,ceilings,rates,u64,normal,f32,lcg52,single,skip,step_valu,engine,batch,serve",
                     help="extra legs to time (comma list or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-lanes", type=int, default=64, help="lanes per segment of the server's plans")
@@ -490,6 +540,9 @@ def main() -> int:
                "sample": f"first {args.cpu_streams} of the 65536 streams x {DRAWS} doubles, p={P} "
                          f"({args.cpu_streams * DRAWS} doubles, {cpu_dt:.1f} s wall on {workers} processes, "
                          f"about {cpu_dt * workers:.0f} CPU-seconds)"}
+    cpu_native = None
+    if "cpu_native" in wanted:
+        cpu_native = cpu_native_leg(min(16, os.cpu_count() or 1), None if args.no_cpu else ref, batch_reqs)
 
     import numpy as np
     import torch
@@ -731,6 +784,7 @@ def main() -> int:
                                 "inside the power-management swing of the first ~50 ms of this load"),
         "order": "cold, legs, headline: the headline is timed after the legs, at the clock the chip settles to",
         "cpu_baseline": cpu,
+        "cpu_native": cpu_native,
         "legs": legs,
         "kernel_sources_sha": sources_sha(),
     }

@@ -20,8 +20,29 @@ FLAGS = [
 ]
 
 
+CPU_SRC = os.path.join(HERE, "cpu", "rlx_cpu.cpp")
+CPU_LIB = os.path.join(HERE, "cpu", "librlx_cpu.so")
+CXX = os.environ.get("CXX", "g++")
+
+
+def build_cpu(verbose: bool = False) -> str:
+    """Compile the CPU baseline (librlx_cpu.so, host C++) and return its path."""
+    tmp = CPU_LIB + ".tmp"
+    cmd = [CXX, "-O3", "-march=x86-64-v3", "-std=c++17", "-fPIC", "-shared", "-pthread", "-o", tmp, CPU_SRC]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        sys.stderr.write(res.stdout + res.stderr)
+        raise RuntimeError("building librlx_cpu.so failed")
+    os.replace(tmp, CPU_LIB)
+    return CPU_LIB
+
+
 def build(verbose: bool = False, extra=()) -> str:
-    """Compile librlx.so unconditionally and return its path."""
+    """Compile librlx.so (and the CPU baseline) unconditionally and return
+    the path of librlx.so."""
+    build_cpu(verbose)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, *FLAGS, *extra, "-o", tmp, *SRC]
     if verbose:
