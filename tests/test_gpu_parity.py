@@ -295,10 +295,18 @@ def test_single_stream_workload_full():
     exp, x_end, pos_end = O.draws(O.seed(1, p), 0, p, count)
     assert u.tolist() == exp
     assert tensor_to_records(st) == [(x_end, pos_end, p)]
+    # every one of the 87 382 trace states against the oracle's successive
+    # multiplications X_{t+1} = A_p X_t mod m from the seed
     tr = trace[0].cpu().numpy()
     nst = count // 12 + 1
-    for t in (0, 1, 2, 1000, 87380, nst - 1):
-        assert words_to_ints(tr[t:t + 1])[0] == O.skip(O.seed(1, p), t, p)
+    assert tr.shape[0] == nst
+    got = words_to_ints(tr)
+    a, x = O.multiplier(p), O.seed(1, p)
+    for t in range(nst):
+        assert got[t] == x, t
+        x = a * x % O.M
+    for t in (0, 1000, nst - 1):                      # and against skip-ahead
+        assert got[t] == O.skip(O.seed(1, p), t, p)
 
 
 def test_many_streams_workload_sampled():
