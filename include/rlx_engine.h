@@ -42,6 +42,7 @@
 
 #include "rlx.h"
 #include "rlx_arith.hpp"
+#include "rlx_gauss.hpp"
 
 /* One generator: the step t being drawn from and its position. */
 struct rlx_engine {
@@ -214,12 +215,9 @@ __device__ __forceinline__ double rlx_engine_next_normal(rlx_engine& e, const rl
     rlx_engine_detail::before_draw(e, t);
     uint32_t w0, w1, w2;
     rlx_engine_detail::pair_words(e, e.pos >> 1, w0, w1, w2);
-    const double u1 = (double)(((uint64_t)(w1 & 0xFFFFu) << 32) | w0) * 0x1p-48;
-    const double u2 = (double)(((uint64_t)(w2 >> 16) << 32) | __builtin_amdgcn_alignbit(w2, w1, 16)) * 0x1p-48;
-    const double r = sqrt(-2.0 * log(1.0 - u1));  /* 1 - u1 is exact */
-    double sn, cs;
-    sincospi(2.0 * u2, &sn, &cs);  /* the bulk kernels' evaluation, so the bits agree */
-    const double z = r * ((e.pos & 1u) ? sn : cs);
+    double zc, zs;
+    rlx::gauss::box_muller(w0, w1, w2, zc, zs);  /* the bulk kernels' evaluation, so the bits agree */
+    const double z = (e.pos & 1u) ? zs : zc;
     rlx_engine_detail::after_draw(e);
     return z;
 }

@@ -6,6 +6,7 @@
 
 #include "rlx.h"
 #include "rlx_arith.hpp"
+#include "rlx_gauss.hpp"
 
 namespace rlx {
 
@@ -168,13 +169,12 @@ __device__ __forceinline__ uint32_t number_f32_bits(uint32_t v) {
 }
 
 // Both output values of the field pair held in words (w0, w1, w2).  For
-// normals, Box-Muller on the pair: r = sqrt(-2 ln(1 - u1)) with u1 the even
-// field's double, and the even and odd positions get r cos(2 pi u2) and
-// r sin(2 pi u2), both from one sincospi (one range reduction); 1 - u1 is in
-// (0, 1] and exact (u1 is a multiple of 2^-48), so log of it is as accurate
-// as log1p(-u1) and cheaper; 2 u2 is exact.  For float32 each position holds its two RANLUX
-// numbers (bits 0..23 and 24..47 of the field), the older one in the low
-// 32 bits, i.e. first in memory.
+// normals, Box-Muller on the pair (rlx_gauss.hpp): the even position gets
+// r cos(2 pi u2) and the odd one r sin(2 pi u2), r = sqrt(-2 ln(1 - u1)).
+// For float32 each position holds its two RANLUX numbers (bits 0..23 and
+// 24..47 of the field), the older one in the low 32 bits, i.e. first in
+// memory; the numbers that straddle a word are gathered by one byte
+// permute each (selector byte 0x0C gives zero).
 template <Out K>
 __device__ __forceinline__ void pair_values(uint32_t w0, uint32_t w1, uint32_t w2, uint64_t& a, uint64_t& b) {
   if constexpr (K == Out::U64) {
@@ -182,24 +182,20 @@ __device__ __forceinline__ void pair_values(uint32_t w0, uint32_t w1, uint32_t w
     b = ((uint64_t)(w2 >> 16) << 32) | __builtin_amdgcn_alignbit(w2, w1, 16);
   } else if constexpr (K == Out::F32) {
     const uint32_t n0 = w0 & 0xFFFFFFu;
-    const uint32_t n1 = __builtin_amdgcn_alignbit(w1, w0, 24) & 0xFFFFFFu;
-    const uint32_t n2 = __builtin_amdgcn_alignbit(w2, w1, 16) & 0xFFFFFFu;
+    const uint32_t n1 = __builtin_amdgcn_perm(w1, w0, 0x0C050403u);  // w0 byte 3, w1 bytes 0, 1
+    const uint32_t n2 = __builtin_amdgcn_perm(w2, w1, 0x0C040302u);  // w1 bytes 2, 3, w2 byte 0
     const uint32_t n3 = w2 >> 8;
     a = ((uint64_t)number_f32_bits(n1) << 32) | number_f32_bits(n0);
     b = ((uint64_t)number_f32_bits(n3) << 32) | number_f32_bits(n2);
   } else {
     double u1, u2;
-    pair_f64(w0, w1, w2, u1, u2);
     if constexpr (K == Out::F64) {
-      a = f64_bits(u1);
-      b = f64_bits(u2);
+      pair_f64(w0, w1, w2, u1, u2);
     } else {
-      const double r = sqrt(-2.0 * log(1.0 - u1));
-      double sn, cs;
-      sincospi(2.0 * u2, &sn, &cs);
-      a = f64_bits(r * cs);
-      b = f64_bits(r * sn);
+      gauss::box_muller(w0, w1, w2, u1, u2);
     }
+    a = f64_bits(u1);
+    b = f64_bits(u2);
   }
 }
 

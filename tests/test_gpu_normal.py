@@ -1,18 +1,20 @@
 """GPU parity of the Gaussian draws (rlx_generate_normal_f64) against the
 mpmath Box-Muller oracle.
 
-The device evaluates log, sqrt and cospi in binary64, each within a few ulp,
+The device evaluates the transform in binary64 (include/rlx_gauss.hpp: an
+exact range reduction for each of log and the angle, series for the rest),
 so values are compared under a tolerance rather than bit for bit:
 
     |gpu - oracle| <= 2^-49 |oracle| + 2^-70
 
-The relative part is 8 ulp of the result: the radius carries the errors of
-log (ocml, about 1 ulp, of the exact 1 - u1) halved by the correctly rounded sqrt, the angle
-factor is cospi of an exactly formed argument (about 1-2 ulp, relative also
-near its zeros because cospi reduces to sinpi there), and the product adds
-half an ulp; 8 ulp leaves a factor of two of margin.  The absolute floor
-covers results that underflow the relative term only when the oracle's value
-is itself below 2^-21 times the floor's scale.
+The relative part is 8 ulp of the result: ln(1 - u1), cos and sin are each
+within about an ulp (tests/test_host_gauss.py measures the same code built
+for the host, whose operations are all correctly rounded, so it computes
+the device's bits), sqrt halves the log's error and rounds once, and the
+product adds half an ulp; the host build's worst case is 2 ulp, and 8 ulp
+leaves a wide margin.  The absolute floor covers the exact zeros of cos and
+sin at quarter turns, which the 40-digit oracle returns as values of about
+10^-41.
 
 Everything that is exact is compared exactly: the records after the call
 (normals consume positions like uniforms do) and the zero of u1 = 0.
