@@ -22,10 +22,13 @@ Legs (reported beside the headline in the same JSON line):
   rates      instruction-rate microbenchmarks (vector multiply-adds, carries,
              float64 adds, int8 matrix-core ops) against the chip's capacity
   u64        the same step writing the 48-bit integers instead of doubles
+  normal     the same streams as standard normals (Box-Muller on field pairs)
   f32        the same streams writing float32, one RANLUX number each
              (8192 per stream: the same 2 GiB), checked against the doubles
   lcg52      the legacy conversion (52 raw LCG bits per double, 11 per
              step; biased, for comparison only), 4096 per stream
+             (each of these four also alternates its kernel with the
+             headline kernel, `same_clock`: kernel times at one clock)
   single     one stream (id 1), 2^20 doubles plus the state after each step
   skip       2^20 seeded states, each skipped by a log-uniform offset in
              [1, 2^64) generator steps
@@ -330,6 +333,29 @@ def timed(fn, stream, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps
 
 
+def paired_kernel_ms(torch, stream, fa, fb, reps: int = 10) -> dict:
+    """Kernel durations of two launches alternated a, b, a, b, ... (HIP
+    events on the launch stream), so both see the same clock: medians of
+    each and their ratio."""
+    import statistics
+    ta, tb = [], []
+    fa()
+    fb()
+    for _ in range(reps):
+        for f, acc in ((fa, ta), (fb, tb)):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            f()
+            e1.record(stream)
+            acc.append((e0, e1))
+    torch.cuda.synchronize()
+    a = statistics.median(x.elapsed_time(y) for x, y in ta)
+    b = statistics.median(x.elapsed_time(y) for x, y in tb)
+    return {"kernel_ms": a, "f64_kernel_ms": b, "ratio_to_f64": a / b, "reps": reps,
+            "note": "kernel alternated with the headline f64 kernel on its own records (same clock)"}
+
+
 def batch_leg(rlx, torch, np, dev, reqs, checks, args):
     """8192 requests (own stream each, p uniform over 5 levels, log-uniform
     counts in [1, 2^20]) in one fused launch; lanes per segment and
@@ -607,6 +633,15 @@ def main() -> int:
         cpu["bit_exact_vs_gpu"] = bit_exact
 
     legs = {}
+    # the headline kernel on records and an output of its own, alternated
+    # with each width's kernel for a same-clock comparison
+    st_ref = rlx.new_states(N_STREAMS, device=dev)
+    rlx.init_streams(st_ref, P, id0=0)
+    out_ref = torch.empty_like(out)
+
+    def f64_ref():
+        rlx.generate_f64(st_ref, DRAWS, P, out=out_ref)
+
     if "ceilings" in wanted:
         # what plain device fills and copies reach on this GPU: the achievable
         # side of the published 8 TB/s (the generate kernel writes 2 GiB)
@@ -629,6 +664,8 @@ def main() -> int:
         dt = timed(step_u, stream, max(5, args.steps // 2), 2, torch)
         legs["u64"] = {"value": total / dt, "unit": "values/s", "ms_per_step": dt * 1e3,
                        "same_bits_as_f64": bool(torch.equal(outu.to(torch.float64) * 2.0 ** -48, out))}
+        legs["u64"]["same_clock"] = paired_kernel_ms(
+            torch, stream, lambda: rlx.generate_u64(st, DRAWS, P, out=outu), f64_ref)
         del outu
     if "single" in wanted:
         st1 = rlx.new_states(1, device=dev)
@@ -669,7 +706,10 @@ def main() -> int:
         legs["normal"] = {"value": total / dt, "unit": "normals/s", "ms_per_step": dt * 1e3,
                           "mean": float(flat.mean()), "var": float(flat.var()),
                           "workload": "many-streams shape, Box-Muller on field pairs"}
-        del outn, flat
+        del flat
+        legs["normal"]["same_clock"] = paired_kernel_ms(
+            torch, stream, lambda: rlx.generate_normal_f64(st, DRAWS, P, out=outn), f64_ref)
+        del outn
     if "f32" in wanted:
         outf = torch.empty((N_STREAMS, 2 * DRAWS), dtype=torch.float32, device=dev)
 
@@ -685,6 +725,8 @@ def main() -> int:
         legs["f32"] = {"value": 2 * total / dt, "unit": "floats/s", "ms_per_step": dt * 1e3,
                        "gb_per_s": 2 * total * 4 / dt / 1e9, "pairs_equal_f64_bits": same,
                        "workload": f"many-streams shape, {2 * DRAWS} float32 per stream (24 per step)"}
+        legs["f32"]["same_clock"] = paired_kernel_ms(
+            torch, stream, lambda: rlx.generate_f32(st, 2 * DRAWS, P, out=outf), f64_ref)
         del outf
     if "lcg52" in wanted:
         out52 = torch.empty((N_STREAMS, DRAWS), dtype=torch.float64, device=dev)
@@ -696,7 +738,10 @@ def main() -> int:
         legs["lcg52"] = {"value": total / dt, "unit": "doubles/s", "ms_per_step": dt * 1e3,
                          "multiples_of_2^-52": bool(((out52 * 2.0 ** 52).frac() == 0).all()),
                          "workload": "many-streams shape, legacy raw-LCG doubles (11 per step)"}
+        legs["lcg52"]["same_clock"] = paired_kernel_ms(
+            torch, stream, lambda: rlx.generate_f64_lcg52(st, DRAWS, P, out=out52), f64_ref)
         del out52
+    del f64_ref, st_ref, out_ref
     if "step_valu" in wanted:
         # the headline step with the other generator-step kernel (and its own
         # lane choice): same values, different instruction mix
