@@ -328,8 +328,8 @@ uint32_t rlx_lanes_per_stream(uint64_t n, uint64_t count);
  *                  with the reduction folded into the multiplier.
  * rlx_set_step_kernel applies to all later calls in the process and returns
  * RLX_EINVAL for any other value; rlx_step_kernel reports the current one.
- * The batch plans (rlx_plan_generate_*) follow the same setting at launch;
- * the legacy 52-bit doubles always use RLX_STEP_VALU. */
+ * The batch plans (rlx_plan_generate_*) and the legacy 52-bit doubles
+ * (rlx_generate_f64_lcg52) follow the same setting at launch. */
 #define RLX_STEP_MFMA 0
 #define RLX_STEP_VALU 1
 int rlx_set_step_kernel(int kind);

@@ -6,7 +6,7 @@
 //   k_init                                 seeding        (section 2.4)
 //   k_skip                                 skip-ahead     (section 2.4)
 //   k_generate<U64|F64|NORMAL|F32, trace, LGS, MF> draw values (sections 2.1-2.3)
-//   k_generate_lcg52<LGS>                  legacy raw-LCG doubles (section 2.3)
+//   k_generate_lcg52<LGS, MF>              legacy raw-LCG doubles (section 2.3)
 //   k_test_*                               generic arithmetic for tests
 // The batched kernel and its planner are in rlx_batch.hip.
 #include <hip/hip_runtime.h>
@@ -390,14 +390,14 @@ __device__ __forceinline__ double lcg52_value(const uint32_t (&x)[NW], int k) {
   return bits_to_f64(lo, (hi & 0xFFFFFu) | 0x3FF00000u) - 1.0;
 }
 
-template <int LGS>
-__global__ __launch_bounds__(BLOCK) void k_generate_lcg52(rlx_state* __restrict__ st, uint32_t n, uint64_t count,
-                                                          double* __restrict__ out,
-                                                          const uint32_t* __restrict__ ctabs,
-                                                          const uint32_t* __restrict__ W, uint32_t lg, uint32_t p,
-                                                          uint32_t* __restrict__ err, int writeback) {
+template <int LGS, bool MF>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MF ? 4 : 5))) void k_generate_lcg52(
+    rlx_state* __restrict__ st, uint32_t n, uint64_t count, double* __restrict__ out,
+    const uint32_t* __restrict__ ctabs, const uint32_t* __restrict__ mtabs, const uint32_t* __restrict__ W,
+    uint32_t lg, uint32_t p, uint32_t* __restrict__ err, int writeback) {
   constexpr uint32_t gs = 1u << LGS;  // lanes of a record inside one wave
   __shared__ double stage[BLOCK * LCG52_VALUES];
+  __shared__ mf_v4i af[MF ? MF_FRAGS * 64 : 1];  // matrix-core operands of A^G, as in k_generate
   const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
   const uint32_t i = (uint32_t)(tid >> lg);
   const uint32_t l = (uint32_t)tid & ((1u << lg) - 1u);
@@ -421,6 +421,10 @@ __global__ __launch_bounds__(BLOCK) void k_generate_lcg52(rlx_state* __restrict_
   const uint32_t nadv = (uint32_t)((pos + count) / LCG52_VALUES);
   skip_windows(x, l, W);
   const uint32_t* __restrict__ ctab = ctabs + (size_t)lg * FOLD_ROW_WORDS;
+  if constexpr (MF) {
+    mf_stage_operands(af, mtabs + (size_t)lg * MF_LEVEL_WORDS, threadIdx.x, BLOCK);
+    __syncthreads();
+  }
   const uint32_t ls = l & (gs - 1);
   double* const slot = stage + (size_t)threadIdx.x * LCG52_VALUES;
   const double* const grp = stage + (size_t)(threadIdx.x - ls) * LCG52_VALUES;
@@ -445,7 +449,13 @@ __global__ __launch_bounds__(BLOCK) void k_generate_lcg52(rlx_state* __restrict_
       }
     }
     wave_sync();
-    if (__any(live && t + (1u << lg) <= nadv)) step(x, constant_table(ctab), false, SgprBarrier());
+    if (__any(live && t + (1u << lg) <= nadv)) {
+      if constexpr (MF) {
+        mfma_step(x, MfFromArray{af, threadIdx.x & 63}, false);
+      } else {
+        step(x, constant_table(ctab), false, SgprBarrier());
+      }
+    }
   }
 }
 
@@ -880,10 +890,16 @@ int generate_lcg52_impl(rlx_state* states, uint64_t n, uint64_t count, double* o
   if (rc) return rc;
   const uint32_t lgs = lg < 6 ? lg : 6;
   const int writeback = lg <= 6;
-#define RLX_GEN52(L)                                                                                  \
-  case L:                                                                                             \
-    k_generate_lcg52<L><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, out, t.C, t.W, lg, p, err, \
-                                               writeback);                                            \
+  const bool mf = g_step_kind.load(std::memory_order_relaxed) == RLX_STEP_MFMA;
+#define RLX_GEN52(L)                                                                                        \
+  case L:                                                                                                   \
+    if (mf) {                                                                                               \
+      k_generate_lcg52<L, true><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, out, t.C, t.M, t.W, lg, p, \
+                                                       err, writeback);                                     \
+    } else {                                                                                                \
+      k_generate_lcg52<L, false><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, out, t.C, t.M, t.W, lg,  \
+                                                        p, err, writeback);                                 \
+    }                                                                                                       \
     break;
   switch (lgs) {
     RLX_GEN52(0) RLX_GEN52(1) RLX_GEN52(2) RLX_GEN52(3) RLX_GEN52(4) RLX_GEN52(5) RLX_GEN52(6)

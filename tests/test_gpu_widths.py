@@ -147,20 +147,25 @@ def test_f32_engine_equals_bulk():
 
 # --- legacy 52-bit doubles --------------------------------------------------------
 
+@pytest.mark.parametrize("kind", (rlx.STEP_MFMA, rlx.STEP_VALU))
 @pytest.mark.parametrize("G", (0, 1, 2, 16, 64, 1024))
-def test_lcg52_matches_oracle(G, lanes_reset):
+def test_lcg52_matches_oracle(G, kind, lanes_reset):
     p = 218
     recs = staggered(37, p, 20 + G, npos=11)
     rlx.set_lanes_per_stream(G)
-    for count in (1, 10, 11, 12, 11 * 40 + 3):
-        st = records_to_tensor(recs)
-        got = rlx.generate_f64_lcg52(st, count, p).cpu().numpy()
-        after = tensor_to_records(st)
-        for i in range(0, 37, 3):
-            x, pos, _ = recs[i]
-            want, x2, pos2 = W.draws_lcg52(x, pos, p, count)
-            assert got[i].tolist() == want, (count, i)
-            assert after[i] == (x2, pos2, p)
+    rlx.set_step_kernel(kind)
+    try:
+        for count in (1, 10, 11, 12, 11 * 40 + 3):
+            st = records_to_tensor(recs)
+            got = rlx.generate_f64_lcg52(st, count, p).cpu().numpy()
+            after = tensor_to_records(st)
+            for i in range(0, 37, 3):
+                x, pos, _ = recs[i]
+                want, x2, pos2 = W.draws_lcg52(x, pos, p, count)
+                assert got[i].tolist() == want, (count, i)
+                assert after[i] == (x2, pos2, p)
+    finally:
+        rlx.set_step_kernel(rlx.STEP_MFMA)
 
 
 def test_lcg52_flags_bad_records():
