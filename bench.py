@@ -165,46 +165,63 @@ def cpu_baseline(n_streams: int, workers: int):
     return res, dt
 
 
-def cpu_native_leg(workers: int, ref=None, batch_reqs=None) -> dict:
+def cpu_native_leg(workers: int, ref=None, batch_reqs=None, reps: int = 5) -> dict:
     """The C++ CPU baseline (paper_2106_02504_amd.cpu: nine 64-bit words,
     unsigned __int128 products, `workers` std::threads) on the survey's
     configurations: C2 in full (65536 streams x 4096 doubles, seeding
     included), C1 block-split over the threads (one stream, 2^20 doubles),
     C3 (2^20 states seeded and skipped by log-uniform offsets) and C4 (the
-    8192-request batch).  Run before any GPU work; values of the first C2
-    streams are compared with the oracle's."""
+    8192-request batch).  Each is the median of `reps` timed runs (steady
+    clock).  Run before any GPU work; values of the first C2 streams are
+    compared with the oracle's."""
+    import statistics
     import numpy as np
     import workloads
     from paper_2106_02504_amd import cpu as rcpu
-    res = {"kind": "native C++ (unsigned __int128, std::thread)", "cores": workers}
-    t0 = time.perf_counter()
-    out = rcpu.generate(N_STREAMS, 0, DRAWS, P, nthreads=workers)
-    dt = time.perf_counter() - t0
+
+    def median_time(fn):
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            r = fn()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts), r
+
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    res = {"kind": "native C++ (unsigned __int128, std::thread)", "cores": workers,
+           "host": {"os_cpu_count": os.cpu_count(), "affinity": affinity}, "timing": f"median of {reps} runs"}
+    dt, out = median_time(lambda: rcpu.generate(N_STREAMS, 0, DRAWS, P, nthreads=workers))
     res["many_streams"] = {"value": N_STREAMS * DRAWS / dt, "unit": "doubles/s", "seconds": dt,
                            "workload": "65536 streams (ids 0..65535) x 4096 doubles, p=2048, seeding included"}
     if ref is not None:
         got = (out[: ref.shape[0]] * 2.0 ** 48).astype(np.uint64)
         res["many_streams"]["bit_exact_vs_oracle"] = bool(np.array_equal(got, ref))
     del out
-    t0 = time.perf_counter()
-    rcpu.generate_split(1, 1 << 20, P, nthreads=workers)
-    dt = time.perf_counter() - t0
+    dt, _ = median_time(lambda: rcpu.generate_split(1, 1 << 20, P, nthreads=workers))
     res["single"] = {"value": (1 << 20) / dt, "unit": "doubles/s", "seconds": dt,
                      "workload": "1 stream (id 1), 2^20 doubles, steps split over the threads by skip"}
     n3 = 1 << 20
-    t0 = time.perf_counter()
-    x = rcpu.seed(n3, 0, P, nthreads=workers)
-    t1 = time.perf_counter()
-    rcpu.skip(x, workloads.skip_offsets(n3), P, nthreads=workers)
-    t2 = time.perf_counter()
-    res["skip"] = {"value": n3 / (t2 - t1), "unit": "states/s", "seconds": t2 - t1, "seed_seconds": t1 - t0,
-                   "workload": "2^20 states, offsets log-uniform in [1, 2^64) steps"}
-    del x
-    if batch_reqs is not None:
+    offs = workloads.skip_offsets(n3)
+    t_seed, x = median_time(lambda: rcpu.seed(n3, 0, P, nthreads=workers))
+    ts = []
+    for _ in range(reps):
+        y = x.copy()
         t0 = time.perf_counter()
-        out, _ = rcpu.generate_requests([r.stream_id for r in batch_reqs], [0] * len(batch_reqs),
-                                        [r.count for r in batch_reqs], [r.p for r in batch_reqs], nthreads=workers)
-        dt = time.perf_counter() - t0
+        rcpu.skip(y, offs, P, nthreads=workers)
+        ts.append(time.perf_counter() - t0)
+    dt = statistics.median(ts)
+    res["skip"] = {"value": n3 / dt, "unit": "states/s", "seconds": dt, "seed_seconds": t_seed,
+                   "workload": "2^20 states, offsets log-uniform in [1, 2^64) steps"}
+    del x, y
+    if batch_reqs is not None:
+        ids = [r.stream_id for r in batch_reqs]
+        counts = [r.count for r in batch_reqs]
+        ps = [r.p for r in batch_reqs]
+        dt, (out, _) = median_time(lambda: rcpu.generate_requests(ids, [0] * len(batch_reqs), counts, ps,
+                                                                   nthreads=workers))
         res["batch"] = {"value": out.shape[0] / dt, "unit": "doubles/s", "seconds": dt,
                         "workload": "8192 requests, own stream each, p over five levels, log-uniform counts"}
         del out
