@@ -232,9 +232,11 @@ int rlx_generate_u64(rlx_state *states, uint64_t n, uint64_t count,
  * s | 1 (u1, u2 their doubles): r cos(2 pi u2) for even s and r sin(2 pi u2)
  * for odd s, r = sqrt(-2 ln(1 - u1)).  So each value depends on its position
  * only, and count normals advance the record by count positions, as count
- * uniforms do.  The transcendental functions are the device's (a few ulp),
- * so results are not bit-identical to a CPU evaluation.  The paper leaves
- * distributions to the framework around the engine (section 2.4). */
+ * uniforms do.  The evaluation (rlx_gauss.hpp) uses only correctly rounded
+ * binary64 operations: within 2 ulp of the exact transform in the host
+ * build's checks, and the same bits on the host as on the device, but not
+ * those of a CPU libm's log, sin and cos.  The paper leaves distributions to
+ * the framework around the engine (section 2.4). */
 int rlx_generate_normal_f64(rlx_state *states, uint64_t n, uint64_t count,
                             double *out, uint32_t p, void *stream);
 

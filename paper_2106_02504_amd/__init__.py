@@ -252,7 +252,7 @@ def generate_u64(states: torch.Tensor, count: int, p: int, out: torch.Tensor | N
 
 def generate_normal_f64(states: torch.Tensor, count: int, p: int, out: torch.Tensor | None = None) -> torch.Tensor:
     """`count` standard normal doubles per record, shape [n, count]: Box-Muller
-    on the field pair of each position's step (device transcendentals)."""
+    on the field pair of each position's step (include/rlx_gauss.hpp)."""
     n = _need_states(states)
     out = _out(states, count, torch.float64, out)
     with torch.cuda.device(states.device):
