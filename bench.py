@@ -13,8 +13,11 @@ Order of the GPU work:
              boosts, cuts the clock hard and recovers over the first ~50 ms of
              this load, and these steps fall in that swing
   legs       the other measurements below, each its own timed region
+  settle     --settle untimed steps of the headline load (default 100,
+             about 45 ms), so the headline does not inherit the clock the
+             last leg left behind
   headline   W untimed warm-up steps, then exactly K timed steps, at the
-             clock the chip settles to under this load (`value`, `roofline`)
+             clock the chip holds under this load (`value`, `roofline`)
 
 Legs (reported beside the headline in the same JSON line):
   ceilings   a plain 2 GiB device fill and a 1 GiB copy: the write and copy
@@ -540,6 +543,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=SETTLE_STEPS)
+    ap.add_argument("--settle", type=int, default=SETTLE_STEPS,
+                    help="untimed steps of the headline load right before the headline's warm-up")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=16384)
     ap.add_argument("--legs",
@@ -792,7 +797,14 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
 
-    # the headline: W untimed warm-up steps, then exactly K timed steps
+    # settle: untimed steps of the headline load itself, so that the clock
+    # the headline sees is the one the chip holds under this load rather
+    # than whatever the last leg left behind; then the headline: W untimed
+    # warm-up steps and exactly K timed steps
+    for _ in range(args.settle):
+        rlx.init_streams(st, P, id0=0)
+        rlx.generate_f64(st, DRAWS, P, out=out)
+    torch.cuda.synchronize()
     head = run_steps(args.warmup, args.steps)
     value = head["value"]
     gen_ms = head["kernel_ms"]
@@ -844,7 +856,9 @@ def main() -> int:
         "compute": compute,
         "cold": dict(cold, note="the same W + K steps as the first GPU work of the process, before the legs: "
                                 "inside the power-management swing of the first ~50 ms of this load"),
-        "order": "cold, legs, headline: the headline is timed after the legs, at the clock the chip settles to",
+        "order": "cold, legs, settle, headline: the headline is timed after the legs and after "
+                 f"{args.settle} untimed steps of its own load, at the clock the chip holds under it",
+        "settle_steps": args.settle,
         "cpu_baseline": cpu,
         "cpu_native": cpu_native,
         "legs": legs,

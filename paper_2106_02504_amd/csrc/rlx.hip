@@ -375,7 +375,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out:
 // these values (0..10).  Same lane interleaving as k_generate (lane l takes
 // steps l, l + G, ...) and the same write-back rule; no RANLUX conversion.
 // A lane's 11 values go through an LDS slot so that each store instruction
-// writes gs consecutive doubles of the row.
+// writes a contiguous run of the row.
 
 constexpr int LCG52_VALUES = 11;
 
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MF ? 4 : 
     const uint32_t* __restrict__ ctabs, const uint32_t* __restrict__ mtabs, const uint32_t* __restrict__ W,
     uint32_t lg, uint32_t p, uint32_t* __restrict__ err, int writeback) {
   constexpr uint32_t gs = 1u << LGS;  // lanes of a record inside one wave
-  __shared__ double stage[BLOCK * LCG52_VALUES];
+  __shared__ __align__(16) double stage[BLOCK * LCG52_VALUES];
   __shared__ mf_v4i af[MF ? MF_FRAGS * 64 : 1];  // matrix-core operands of A^G, as in k_generate
   const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
   const uint32_t i = (uint32_t)(tid >> lg);
@@ -438,10 +438,24 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(MF ? 4 : 
 #pragma unroll
     for (int f = 0; f < LCG52_VALUES; ++f) slot[f] = lcg52_value(x, f);
     wave_sync();
-    // the group's blocks t - ls .. t - ls + gs - 1 hold values from u0 on;
-    // value q gs + ls of the group goes to row[u0 + q gs + ls] if in range
-    if (active) {
-      uint64_t u = (uint64_t)((int64_t)((uint64_t)(t - ls) * LCG52_VALUES) - (int64_t)pos + (int64_t)ls);
+    // the group's blocks t - ls .. t - ls + gs - 1 hold values from u0 on.
+    // A whole wave of whole windows starting on 128-byte lines stores 16-byte
+    // pairs: lane ls takes pairs q gs + ls of the group's 11 gs / 2, so each
+    // instruction writes 16 gs contiguous bytes per group (the last one with
+    // half the lanes).  Otherwise value q gs + ls goes to row[u0 + q gs + ls]
+    // if in range.
+    const int64_t u0 = (int64_t)((uint64_t)(t - ls) * LCG52_VALUES) - (int64_t)pos;
+    const bool whole = u0 >= 0 && (uint64_t)u0 + LCG52_VALUES * gs <= count;
+    const uint64_t a = reinterpret_cast<uint64_t>(out) + ((uint64_t)i * count + (uint64_t)u0) * sizeof(double);
+    if (gs >= 8 && __all(active && whole && (a & 127) == 0)) {
+      const ulonglong2* g2 = reinterpret_cast<const ulonglong2*>(grp) + ls;
+      uint64_t* const dst = reinterpret_cast<uint64_t*>(row + u0) + 2 * ls;
+#pragma unroll
+      for (uint32_t q = 0; q < (LCG52_VALUES + 1) / 2; ++q) {
+        if (q * gs + ls < LCG52_VALUES * gs / 2) store_pair<true>(dst + 2 * q * gs, g2[q * gs]);
+      }
+    } else if (active) {
+      uint64_t u = (uint64_t)(u0 + (int64_t)ls);
 #pragma unroll
       for (int q = 0; q < LCG52_VALUES; ++q) {
         if (u < count) row[u] = grp[q * gs + ls];

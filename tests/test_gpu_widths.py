@@ -182,6 +182,25 @@ def test_lcg52_flags_bad_records():
     assert o[4].tolist() == W.draws_lcg52(7, 10, p, 4)[0]
 
 
+@pytest.mark.parametrize("G", (8, 32, 64))
+def test_lcg52_whole_window_pair_stores(G, lanes_reset):
+    # records at position 0 with 4096-value rows: whole waves of whole
+    # windows on 128-byte lines take the 16-byte pair stores; an odd
+    # position, rows that are not multiples of 128 bytes and a ragged count
+    # take the per-value stores; every value against the oracle
+    p = 2048
+    rlx.set_lanes_per_stream(G)
+    for pos, count in ((0, 4096), (0, 1000), (1, 4096), (0, 4096 + 11)):
+        recs = [(O.seed(100 + i, p), pos, p) for i in range(24)]
+        st = records_to_tensor(recs)
+        got = rlx.generate_f64_lcg52(st, count, p).cpu().numpy()
+        after = tensor_to_records(st)
+        for i in range(24):
+            want, x2, pos2 = W.draws_lcg52(recs[i][0], pos, p, count)
+            assert got[i].tolist() == want, (G, pos, count, i)
+            assert after[i] == (x2, pos2, p)
+
+
 def test_lcg52_many_streams_workload_sampled():
     p, n, count = 2048, 65536, 4096
     st = rlx.new_states(n)
