@@ -376,7 +376,7 @@ def paired_kernel_ms(torch, stream, fa, fb, reps: int = 10) -> dict:
             "note": "kernel alternated with the headline f64 kernel on its own records (same clock)"}
 
 
-def batch_leg(rlx, torch, np, dev, reqs, checks, args):
+def batch_leg(rlx, torch, np, dev, reqs, checks, args, plain=None):
     """8192 requests (own stream each, p uniform over 5 levels, log-uniform
     counts in [1, 2^20]) in one fused launch; lanes per segment and
     segment length from the autotuner; also replayed from a HIP graph."""
@@ -414,9 +414,14 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
     g.replay()
     torch.cuda.synchronize()
     reps = max(20, args.steps // 4)
-    direct, replay = [], []
+    direct, replay, ref = [], [], []
+    seq = [(lambda: plan.generate_f64(st, out), direct), (g.replay, replay)]
+    if plain is not None:
+        # the plain headline kernel in the same alternation: the batch's
+        # rate relative to it at the same clock
+        seq.append((plain[0], ref))
     for _ in range(reps):
-        for fn, acc in ((lambda: plan.generate_f64(st, out), direct), (g.replay, replay)):
+        for fn, acc in seq:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -436,7 +441,13 @@ def batch_leg(rlx, torch, np, dev, reqs, checks, args):
                 exact &= got.view(np.uint64).tolist() == vals
     info = plan.info()
     plan.close()
-    return {"value": total / (gms * 1e-3), "unit": "doubles/s", "graph_replay_ms": gms,
+    same = None
+    if plain is not None:
+        pms = float(np.median(ref))
+        same = {"plain_kernel_ms": pms, "plain_doubles_per_s": plain[1] / (pms * 1e-3),
+                "fraction_of_plain": (total / (gms * 1e-3)) / (plain[1] / (pms * 1e-3)),
+                "note": "the plain many-streams kernel alternated with the batch launches (same clock)"}
+    return {"value": total / (gms * 1e-3), "unit": "doubles/s", "graph_replay_ms": gms, "same_clock": same,
             "direct_ms": ms, "direct_value": total / (ms * 1e-3), "reps": reps,
             "timing": "value from HIP-graph replays; direct launches and replays alternate, medians of each",
             "lanes_per_segment": tuned["lanes"], "seg_blocks": tuned["seg_blocks"],
@@ -763,7 +774,6 @@ def main() -> int:
         legs["lcg52"]["same_clock"] = paired_kernel_ms(
             torch, stream, lambda: rlx.generate_f64_lcg52(st, DRAWS, P, out=out52), f64_ref)
         del out52
-    del f64_ref, st_ref, out_ref
     if "step_valu" in wanted:
         # the headline step with the other generator-step kernel (and its own
         # lane choice): same values, different instruction mix
@@ -783,8 +793,9 @@ def main() -> int:
 
     if "batch" in wanted:
         del out
-        legs["batch"] = batch_leg(rlx, torch, np, dev, batch_reqs, checks, args)
+        legs["batch"] = batch_leg(rlx, torch, np, dev, batch_reqs, checks, args, plain=(f64_ref, total))
         out = torch.empty((N_STREAMS, DRAWS), dtype=torch.float64, device=dev)
+    del f64_ref, st_ref, out_ref
 
     if "serve" in wanted:
         legs["serve"] = serve_leg(rlx, torch, np, dev, args, serve_checks)
