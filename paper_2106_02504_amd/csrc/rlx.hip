@@ -290,8 +290,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out:
   // Per-lane state kept across the loop is x plus four 32-bit words (record
   // index, lane, pos, last block): the host limits n < 2^32 and
   // count <= RLX_MAX_COUNT, so record and block indices fit in 32 bits.
-  // Everything else is recomputed per iteration, which keeps the kernel at
-  // eight waves per SIMD.
+  // Everything else is recomputed per iteration, which keeps the registers
+  // within 128 (4 waves per SIMD; 3 for normals) without spills.
   constexpr bool STAGED = LGS > 0;
   constexpr uint32_t gs = 1u << LGS;  // lanes of a record inside one wave
   __shared__ __align__(16) uint64_t stage[STAGED ? BLOCK * SLOT_VALUES : 2];
