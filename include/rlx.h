@@ -93,7 +93,8 @@ enum {
 #define RLX_MAX_SEG_BLOCKS (1ull << 26)
 
 /* Error-word bits reported by rlx_check_errors(). */
-#define RLX_ERR_BAD_P    0x1u   /* record's p differs from the call's p */
+#define RLX_ERR_BAD_P    0x1u   /* record's p differs from the call's p (or,
+                                   with RLX_P_RECORD, is not prepared) */
 #define RLX_ERR_BAD_POS  0x2u   /* record's pos > 11 */
 #define RLX_ERR_BAD_X    0x4u   /* record's X >= m */
 #define RLX_ERR_NOT_CANONICAL 0x8u  /* imported RANLUX state is not canonical */
@@ -200,6 +201,24 @@ int rlx_get_tables(uint32_t p, rlx_engine_tables *out, void *stream);
  * uint64 or NULL; id0 + n - 1 must not overflow 64 bits. */
 int rlx_init_streams(rlx_state *states, uint64_t n, const uint64_t *ids,
                      uint64_t id0, uint32_t p, void *stream);
+
+/* Records of several luxury levels in one call.  Passing p = RLX_P_RECORD
+ * to rlx_skip, rlx_skip_values, rlx_generate_f64, rlx_generate_u64,
+ * rlx_generate_normal_f64 or rlx_generate_f32 uses each record's own level
+ * (its `p` field) instead of one level for all.  Every level that occurs
+ * must already be prepared on the device (rlx_prepare, or an earlier call
+ * with that p); records of any other level are flagged RLX_ERR_BAD_P and
+ * left unchanged, their outputs unwritten.  With more than
+ * RLX_MAX_RECORD_LEVELS levels prepared on the device such a call returns
+ * RLX_EINVAL.  A generate call then uses at most 64 lanes per record.  A
+ * wave whose records share one level runs that level's step as a uniform
+ * p call does; a wave that mixes levels multiplies lane by lane (about five
+ * times the vector work per step), so records sorted by level run fastest.
+ * rlx_init_streams, rlx_generate_f64_trace, rlx_generate_f64_lcg52 and
+ * rlx_import_ranlux take one level (RLX_P_RECORD -> RLX_EINVAL); batch plans
+ * mix levels per request (rlx_plan_create). */
+#define RLX_P_RECORD 0u
+#define RLX_MAX_RECORD_LEVELS 16
 
 /* Skip-ahead (section 2.4).  For every record i with luxury level p:
  *   x <- A_p^k x mod m, pos unchanged,

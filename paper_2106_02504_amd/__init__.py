@@ -146,6 +146,9 @@ def new_states(n: int, device: str | torch.device = "cuda") -> torch.Tensor:
     return torch.zeros((n, STATE_WORDS), dtype=torch.int64, device=device)
 
 
+P_RECORD = 0   # p for skip/generate calls that use each record's own luxury level
+
+
 def prepare(p: int) -> None:
     """Build the tables of luxury level p on the current device now."""
     _check(lib().rlx_prepare(p, _stream()), "rlx_prepare")
@@ -163,7 +166,8 @@ def init_streams(states: torch.Tensor, p: int, ids: torch.Tensor | None = None, 
 
 def skip(states: torch.Tensor, steps, p: int) -> torch.Tensor:
     """Advance every record by `steps` generator steps (12 values each):
-    an int for all, or a device tensor of n uint64/int64 (section 2.4)."""
+    an int for all, or a device tensor of n uint64/int64 (section 2.4).
+    p = P_RECORD uses each record's own (prepared) level."""
     n = _need_states(states)
     if isinstance(steps, torch.Tensor):
         _need_u64_vector(steps, n, "steps")
@@ -233,7 +237,10 @@ def _out(states: torch.Tensor, count: int, dtype: torch.dtype, out: torch.Tensor
 
 
 def generate_f64(states: torch.Tensor, count: int, p: int, out: torch.Tensor | None = None) -> torch.Tensor:
-    """`count` uniform doubles per record, shape [n, count] (section 2.3)."""
+    """`count` uniform doubles per record, shape [n, count] (section 2.3).
+    p = P_RECORD draws each record at its own level (every level present
+    prepared first); so do generate_u64, generate_f32 and
+    generate_normal_f64."""
     n = _need_states(states)
     out = _out(states, count, torch.float64, out)
     with torch.cuda.device(states.device):

@@ -4,8 +4,9 @@
 //   k_tab_base / k_tab_fill / k_tab_fold / k_tab_win   per-luxury-level tables
 //   k_tab_mf_c / k_tab_mf_k / k_tab_mf_frag          matrix-core operands of a step
 //   k_init                                 seeding        (section 2.4)
-//   k_skip                                 skip-ahead     (section 2.4)
+//   k_skip, k_skip_levels                  skip-ahead     (section 2.4)
 //   k_generate<U64|F64|NORMAL|F32, trace, LGS, MF> draw values (sections 2.1-2.3)
+//   k_generate_levels<K, LGS>              the same for records of several levels
 //   k_generate_lcg52<LGS, MF>              legacy raw-LCG doubles (section 2.3)
 //   k_test_*                               generic arithmetic for tests
 // The batched kernel and its planner are in rlx_batch.hip.
@@ -253,6 +254,64 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
   store_record(st, i, x, pos, sp);
 }
 
+// Records of several luxury levels in one call (p = RLX_P_RECORD): the
+// tables of every level prepared on the device, passed by value.  A record
+// whose level is not among them is flagged RLX_ERR_BAD_P and left as it is.
+constexpr int MAX_RECORD_LEVELS = RLX_MAX_RECORD_LEVELS;
+struct LevelSet {
+  uint32_t n;
+  uint32_t p[MAX_RECORD_LEVELS];
+  const uint32_t* C[MAX_RECORD_LEVELS];
+  const uint32_t* M[MAX_RECORD_LEVELS];
+  const uint32_t* W[MAX_RECORD_LEVELS];
+};
+
+// Index of level p in L, or -1.
+__device__ __forceinline__ int level_index(const LevelSet& L, uint32_t p) {
+  int li = -1;
+#pragma unroll
+  for (int k = 0; k < MAX_RECORD_LEVELS; ++k)
+    if (k < (int)L.n && L.p[k] == p) li = k;
+  return li;
+}
+
+// L's table pointer of entry li (a chain of selects over the unrolled
+// entries, so the by-value argument is never indexed dynamically).
+__device__ __forceinline__ const uint32_t* level_ptr(const uint32_t* const (&tab)[MAX_RECORD_LEVELS], int li) {
+  const uint32_t* r = tab[0];
+#pragma unroll
+  for (int k = 1; k < MAX_RECORD_LEVELS; ++k)
+    if (k == li) r = tab[k];
+  return r;
+}
+
+// k_skip with each record's own level.
+__global__ __launch_bounds__(BLOCK) void k_skip_levels(rlx_state* __restrict__ st, uint64_t n,
+                                                       const uint64_t* __restrict__ steps, uint64_t steps0,
+                                                       LevelSet L, uint32_t* __restrict__ err, int by_values,
+                                                       uint32_t per_step) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint32_t x[NW], pos, sp;
+  load_record(st, i, x, pos, sp);
+  const int li = level_index(L, sp);
+  uint32_t bad = check_record(x, pos, sp, sp) | (li < 0 ? RLX_ERR_BAD_P : 0u);
+  if (by_values && pos >= per_step) bad |= RLX_ERR_BAD_POS;
+  if (bad) {
+    atomicOr(err, bad);
+    return;
+  }
+  uint64_t k = steps ? steps[i] : steps0;
+  if (by_values) {
+    const uint64_t v = k;
+    const uint32_t r = pos + (uint32_t)(v % per_step);
+    k = v / per_step + r / per_step;
+    pos = r % per_step;
+  }
+  skip_windows(x, k, level_ptr(L.W, li));
+  store_record(st, i, x, pos, sp);
+}
+
 // ---------------------------------------------------------------------------
 // generation (sections 2.1-2.3)
 
@@ -363,6 +422,84 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out:
         mfma_step(x, MfFromArray{af, threadIdx.x & 63}, force);
       } else {
         step(x, constant_table(ctab), force, SgprBarrier());
+      }
+    }
+  }
+}
+
+// k_generate for records of several levels (p = RLX_P_RECORD), G <= 64 lanes
+// per record, so a record's lanes share a wave and write it back in place.
+// A wave whose live records all have one level takes that level's
+// matrix-core step (operands read through the L1, as the batched kernel does
+// for items of mixed levels); a wave that mixes levels multiplies each lane
+// by its own level's A^G with the generic multiplication.
+template <Out K, int LGS>
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out::NORMAL ? 3 : 4))) void k_generate_levels(
+    rlx_state* __restrict__ st, uint32_t n, uint64_t count, uint64_t* __restrict__ out, LevelSet L, uint32_t lg,
+    uint32_t* __restrict__ err) {
+  constexpr bool STAGED = LGS > 0;
+  constexpr uint32_t gs = 1u << LGS;
+  __shared__ __align__(16) uint64_t stage[STAGED ? BLOCK * SLOT_VALUES : 2];
+  const uint64_t tid = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const uint32_t i = (uint32_t)(tid >> lg);
+  const uint32_t l = (uint32_t)tid & ((1u << lg) - 1u);
+
+  uint32_t x[NW];
+  uint32_t pos = 0, sp = 0;
+  int li = -1;
+  bool active = (tid >> lg) < n;
+  if (active) {
+    load_record(st, i, x, pos, sp);
+    li = level_index(L, sp);
+    const uint32_t bad = check_record(x, pos, sp, sp) | (li < 0 ? RLX_ERR_BAD_P : 0u);
+    if (bad) {
+      if (l == 0) atomicOr(err, bad);
+      active = false;
+    }
+  }
+  if (!active) {
+    set_one(x);
+    pos = 0;
+    li = -1;
+  }
+  // the wave's level when all its live records share one
+  const uint64_t act = __ballot(li >= 0);
+  const int first = act ? __ffsll((unsigned long long)act) - 1 : 0;
+  const int u = __builtin_amdgcn_readfirstlane(__shfl(li, first));
+  const bool uniform = __all(li < 0 || li == u);
+  const uint32_t nadv = (uint32_t)((pos + count) / FIELDS);
+  if (STAGED && active) skip_windows(x, l, level_ptr(L.W, li));
+
+  for (uint32_t k = 0;; ++k) {
+    const uint32_t t = l + (k << lg);
+    const bool live = active && t <= nadv;
+    if (!__any(live)) break;
+    if (live && t == nadv) store_record(st, i, x, (uint32_t)((pos + count) % FIELDS), sp);
+    uint64_t* const row = out + (uint64_t)i * count;
+    if (!STAGED) {
+      uint32_t d[NW];
+      to_ranlux(x, d, false);
+      if (live) {
+        const int64_t jb = (int64_t)((uint64_t)t * FIELDS) - (int64_t)pos;
+#pragma unroll
+        for (int f = 0; f < FIELDS; ++f) {
+          const int64_t j = jb + f;
+          if (j >= 0 && (uint64_t)j < count) row[j] = field_bits<K>(d, f);
+        }
+      }
+    } else {
+      const uint32_t ls = l & (gs - 1);
+      convert_to_lds<K>(x, stage + (size_t)threadIdx.x * SLOT_VALUES, false);
+      const int64_t jb = (int64_t)((uint64_t)(t - ls) * FIELDS) - (int64_t)pos;
+      group_store<LGS>(stage, threadIdx.x, ls, jb, count, active, row);
+    }
+    if (__any(live && t + (1u << lg) <= nadv)) {
+      if (uniform) {
+        mfma_step(x, MfFromBuffer(level_ptr(L.M, u) + (size_t)lg * MF_LEVEL_WORDS, threadIdx.x & 63), false);
+      } else if (active) {
+        uint32_t a[NW];
+        load_words(level_ptr(L.C, li) + (size_t)lg * FOLD_ROW_WORDS, a);  // C_0 = A^G
+        mulmod_inplace(x, a);
       }
     }
   }
@@ -820,12 +957,14 @@ uint32_t lanes_for(uint64_t n, uint64_t count) {
 // Argument checks shared by the generate calls; on success *lg is log2 of
 // the lanes per record and *grid covers n << lg lanes.
 int generate_args(const rlx_state* states, uint64_t n, uint64_t count, const void* out, uint32_t p,
-                  uint32_t* lg, dim3* grid) {
-  if (!states || !out || !valid_p(p)) return RLX_EINVAL;
+                  uint32_t* lg, dim3* grid, bool record_levels = false) {
+  if (!states || !out) return RLX_EINVAL;
+  if (record_levels ? p != RLX_P_RECORD : !valid_p(p)) return RLX_EINVAL;
   if (!aligned(states, 16) || !aligned(out, 8)) return RLX_EINVAL;
   if (n > RLX_MAX_STREAMS || count > RLX_MAX_COUNT) return RLX_EINVAL;
   if (count > UINT64_MAX / 8 / n) return RLX_EINVAL;
-  const uint32_t G = lanes_for(n, count);
+  uint32_t G = lanes_for(n, count);
+  if (record_levels && G > 64) G = 64;  // a record's lanes in one wave
   *lg = (uint32_t)__builtin_ctz(G);
   if (n > (UINT64_MAX >> *lg)) return RLX_EINVAL;
   return grid_for(n << *lg, grid) ? RLX_OK : RLX_EINVAL;
@@ -847,9 +986,59 @@ int advance_after(rlx_state* states, uint64_t n, uint64_t count, uint32_t per_st
   return launch_status();
 }
 
+// The tables of every level prepared on the current device, for the calls
+// with p = RLX_P_RECORD; RLX_EINVAL beyond RLX_MAX_RECORD_LEVELS levels.
+int level_set(LevelSet* L) {
+  int dev;
+  if (current_device(&dev)) return RLX_EHIP;
+  std::lock_guard<std::mutex> lk(g_mu);
+  *L = LevelSet{};
+  for (const auto& kv : g_tables) {
+    if (kv.first.first != dev) continue;
+    if (L->n == (uint32_t)MAX_RECORD_LEVELS) return RLX_EINVAL;
+    L->p[L->n] = kv.first.second;
+    L->C[L->n] = kv.second.C;
+    L->M[L->n] = kv.second.M;
+    L->W[L->n] = kv.second.W;
+    ++L->n;
+  }
+  return RLX_OK;
+}
+
+template <Out K>
+int generate_levels_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, void* stream) {
+  if (n == 0 || count == 0) return RLX_OK;
+  uint32_t lg;
+  dim3 grid;
+  int rc = generate_args(states, n, count, out, RLX_P_RECORD, &lg, &grid, true);
+  if (rc) return rc;
+  hipStream_t s = as_stream(stream);
+  LevelSet L;
+  rc = level_set(&L);
+  if (rc) return rc;
+  uint32_t* err;
+  rc = error_word(s, &err);
+  if (rc) return rc;
+  uint64_t* o = reinterpret_cast<uint64_t*>(out);
+#define RLX_GENL(LG)                                                                                  \
+  case LG:                                                                                            \
+    k_generate_levels<K, LG><<<grid, BLOCK, 0, s>>>(states, (uint32_t)n, count, o, L, lg, err);       \
+    break;
+  switch (lg) {
+    RLX_GENL(0) RLX_GENL(1) RLX_GENL(2) RLX_GENL(3) RLX_GENL(4) RLX_GENL(5) RLX_GENL(6)
+    default: return RLX_EINVAL;
+  }
+#undef RLX_GENL
+  return launch_status();
+}
+
 template <Out K, bool TRACE>
 int generate_impl(rlx_state* states, uint64_t n, uint64_t count, void* out, uint64_t* trace,
                   uint64_t trace_steps, uint32_t p, void* stream, int force_general) {
+  if (p == RLX_P_RECORD) {
+    if (TRACE || force_general) return RLX_EINVAL;
+    return generate_levels_impl<K>(states, n, count, out, stream);
+  }
   if (n == 0 || count == 0) return RLX_OK;
   uint32_t lg;
   dim3 grid;
@@ -1010,15 +1199,24 @@ int rlx_init_streams(rlx_state* states, uint64_t n, const uint64_t* ids, uint64_
 int rlx_skip(rlx_state* states, uint64_t n, const uint64_t* steps, uint64_t steps0, uint32_t p,
              void* stream) {
   if (n == 0) return RLX_OK;
-  if (!states || !valid_p(p) || !aligned(states, 16)) return RLX_EINVAL;
+  if (!states || !(valid_p(p) || p == RLX_P_RECORD) || !aligned(states, 16)) return RLX_EINVAL;
   if (steps && !aligned(steps, 8)) return RLX_EINVAL;
   dim3 grid;
   if (!grid_for(n, &grid)) return RLX_EINVAL;
   hipStream_t s = as_stream(stream);
+  uint32_t* err;
+  if (p == RLX_P_RECORD) {
+    LevelSet L;
+    int rc = level_set(&L);
+    if (rc) return rc;
+    rc = error_word(s, &err);
+    if (rc) return rc;
+    k_skip_levels<<<grid, BLOCK, 0, s>>>(states, n, steps, steps0, L, err, 0, FIELDS);
+    return launch_status();
+  }
   Tables t;
   int rc = tables(p, s, &t);
   if (rc) return rc;
-  uint32_t* err;
   rc = error_word(s, &err);
   if (rc) return rc;
   k_skip<<<grid, BLOCK, 0, s>>>(states, n, steps, steps0, p, t.W, err, 0, FIELDS);
@@ -1028,15 +1226,24 @@ int rlx_skip(rlx_state* states, uint64_t n, const uint64_t* steps, uint64_t step
 int rlx_skip_values(rlx_state* states, uint64_t n, const uint64_t* values, uint64_t values0, uint32_t p,
                     void* stream) {
   if (n == 0) return RLX_OK;
-  if (!states || !valid_p(p) || !aligned(states, 16)) return RLX_EINVAL;
+  if (!states || !(valid_p(p) || p == RLX_P_RECORD) || !aligned(states, 16)) return RLX_EINVAL;
   if (values && !aligned(values, 8)) return RLX_EINVAL;
   dim3 grid;
   if (!grid_for(n, &grid)) return RLX_EINVAL;
   hipStream_t s = as_stream(stream);
+  uint32_t* err;
+  if (p == RLX_P_RECORD) {
+    LevelSet L;
+    int rc = level_set(&L);
+    if (rc) return rc;
+    rc = error_word(s, &err);
+    if (rc) return rc;
+    k_skip_levels<<<grid, BLOCK, 0, s>>>(states, n, values, values0, L, err, 1, FIELDS);
+    return launch_status();
+  }
   Tables t;
   int rc = tables(p, s, &t);
   if (rc) return rc;
-  uint32_t* err;
   rc = error_word(s, &err);
   if (rc) return rc;
   k_skip<<<grid, BLOCK, 0, s>>>(states, n, values, values0, p, t.W, err, 1, FIELDS);

@@ -95,6 +95,29 @@ def test_other_widths_argument_checks(rlx):
     assert lib.rlx_test_engine(v(16), 5, 10, v(16), 8, 2048, None) == 1
 
 
+def test_record_level_argument_checks(rlx):
+    lib = rlx.lib()
+    v = ctypes.c_void_p
+    assert rlx.P_RECORD == 0
+    hdr = open(os.path.join(ROOT, "include", "rlx.h")).read()
+    assert "#define RLX_P_RECORD 0u" in hdr and "#define RLX_MAX_RECORD_LEVELS 16" in hdr
+    # one-level entry points refuse the per-record level
+    assert lib.rlx_init_streams(v(16), 5, None, 0, 0, None) == 1
+    assert lib.rlx_generate_f64_trace(v(16), 5, 10, v(16), v(16), 100, 0, None) == 1
+    assert lib.rlx_generate_f64_lcg52(v(16), 5, 10, v(16), 0, None) == 1
+    assert lib.rlx_test_generate_u64_general(v(16), 5, 10, v(16), 0, None) == 1
+    # the per-record calls keep the argument checks of the others
+    assert lib.rlx_generate_f64(v(16), 5, 10, v(12), 0, None) == 1
+    assert lib.rlx_generate_u64(v(16), 1 << 32, 1, v(16), 0, None) == 1
+    assert lib.rlx_generate_f32(v(16), 5, 7, v(16), 0, None) == 1
+    assert lib.rlx_skip(v(16), 5, v(12), 0, 0, None) == 1
+    assert lib.rlx_skip_values(None, 5, None, 0, 0, None) == 1
+    # no-ops
+    assert lib.rlx_generate_f64(None, 0, 10, None, 0, None) == 0
+    assert lib.rlx_generate_normal_f64(None, 5, 0, None, 0, None) == 0
+    assert lib.rlx_skip(None, 0, None, 0, 0, None) == 0
+
+
 def test_automatic_lanes_per_stream(rlx):
     # host-only pick of lanes per record: powers of two within the launch
     # and step limits; more lanes for few streams, whole waves otherwise.
