@@ -32,6 +32,8 @@ Legs (reported beside the headline in the same JSON line):
              step; biased, for comparison only), 4096 per stream
              (each of these four also alternates its kernel with the
              headline kernel, `same_clock`: kernel times at one clock)
+  levels     the same shape with records of five luxury levels in one call
+             (p = RLX_P_RECORD), in level blocks and shuffled
   single     one stream (id 1), 2^20 doubles plus the state after each step
   skip       2^20 seeded states, each skipped by a log-uniform offset in
              [1, 2^64) generator steps
@@ -559,7 +561,7 @@ def main() -> int:
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-streams", type=int, default=16384)
     ap.add_argument("--legs",
-                    default="cpu_native,ceilings,rates,u64,normal,f32,lcg52,single,skip,step_valu,engine,batch,serve",
+                    default="cpu_native,ceilings,rates,u64,normal,f32,lcg52,levels,single,skip,step_valu,engine,batch,serve",
                     help="extra legs to time (comma list or 'none')")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-lanes", type=int, default=64, help="lanes per segment of the server's plans")
@@ -774,6 +776,31 @@ def main() -> int:
         legs["lcg52"]["same_clock"] = paired_kernel_ms(
             torch, stream, lambda: rlx.generate_f64_lcg52(st, DRAWS, P, out=out52), f64_ref)
         del out52
+    if "levels" in wanted:
+        # records of the five batch levels in one call (p = RLX_P_RECORD):
+        # the many-streams shape with the records in level blocks (waves of
+        # one level) and shuffled (nearly every wave mixes levels)
+        import workloads
+        lv = workloads.LUXURY_LEVELS
+        stl = rlx.new_states(N_STREAMS, device=dev)
+        per = N_STREAMS // len(lv)
+        for k, pl in enumerate(lv):
+            hi = N_STREAMS if k == len(lv) - 1 else (k + 1) * per
+            rlx.init_streams(stl[k * per:hi], pl, id0=k * per)
+        gen = torch.Generator().manual_seed(9)
+        sts = stl[torch.randperm(N_STREAMS, generator=gen).to(dev)].contiguous()
+        outl = torch.empty_like(out)
+        legs["levels"] = {
+            "workload": f"65536 streams x {DRAWS} doubles, levels {list(lv)} in blocks of {per}, "
+                        "p = RLX_P_RECORD",
+            "blocks": paired_kernel_ms(torch, stream, lambda: rlx.generate_f64(stl, DRAWS, rlx.P_RECORD, out=outl),
+                                       f64_ref),
+            "shuffled": paired_kernel_ms(torch, stream,
+                                         lambda: rlx.generate_f64(sts, DRAWS, rlx.P_RECORD, out=outl), f64_ref,
+                                         reps=3)}
+        for k in ("blocks", "shuffled"):
+            legs["levels"][k]["doubles_per_s"] = total / (legs["levels"][k]["kernel_ms"] * 1e-3)
+        del stl, sts, outl
     if "step_valu" in wanted:
         # the headline step with the other generator-step kernel (and its own
         # lane choice): same values, different instruction mix

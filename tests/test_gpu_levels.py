@@ -59,7 +59,7 @@ def test_generate_f64_each_record_at_its_level(G, sort):
 
 def test_uniform_waves_many_streams_shape():
     # 4096 streams in five level blocks of 819 (waves of one level at G = 32,
-    # but for the two straddling each block boundary), 4096
+    # but for the one straddling each block boundary), 4096
     # values: the matrix-core path; every 97th row against the oracle
     rlx.set_lanes_per_stream(0)
     n, count = 4096, 4096
