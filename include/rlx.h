@@ -212,8 +212,10 @@ int rlx_init_streams(rlx_state *states, uint64_t n, const uint64_t *ids,
  * RLX_MAX_RECORD_LEVELS levels prepared on the device such a call returns
  * RLX_EINVAL.  A generate call then uses at most 64 lanes per record.  A
  * wave whose records share one level runs that level's step as a uniform
- * p call does; a wave that mixes levels multiplies lane by lane (about five
- * times the vector work per step), so records sorted by level run fastest.
+ * p call does; a wave that mixes levels multiplies lane by lane (several
+ * times the vector work of a step: fully shuffled levels took 1.8 times the
+ * one-level kernel's time on 65536 streams x 4096 doubles, level blocks
+ * 1.1 times), so records sorted by level run fastest.
  * rlx_init_streams, rlx_generate_f64_trace, rlx_generate_f64_lcg52 and
  * rlx_import_ranlux take one level (RLX_P_RECORD -> RLX_EINVAL); batch plans
  * mix levels per request (rlx_plan_create). */
