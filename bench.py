@@ -76,7 +76,7 @@ MFMA_OPS = 2 * 32 * 32 * 32       # operations of one v_mfma_i32_32x32x32_i8
 MATRIX_OPS_PER_DOUBLE = 2 * 73 * 73 / 12   # a step's contraction: 72 input bytes + the constant
                                            # column by 73 output digits, per 12 doubles
 KERNEL_SOURCES = ("paper_2106_02504_amd/csrc/rlx.hip", "include/rlx_arith.hpp",
-                  "paper_2106_02504_amd/csrc/rlx_device.hpp", "paper_2106_02504_amd/csrc/rlx_mfma.hpp")
+                  "paper_2106_02504_amd/csrc/rlx_device.hpp", "include/rlx_mfma.hpp")
 
 
 # ---------------------------------------------------------------------------

@@ -145,7 +145,8 @@ typedef struct rlx_engine_tables {
     uint32_t reserved;
     const uint32_t *mfma;       /* RLX_FOLD_G * RLX_MFMA_ROW_WORDS words: the
                                    matrix-core operands of a step by 2^g
-                                   steps (not used by the engine) */
+                                   steps (row 0: the engine's step; NULL
+                                   keeps the engine on the vector step) */
 } rlx_engine_tables;
 
 /* Words of one step size's matrix-core operands: nine A operands of
@@ -210,12 +211,12 @@ int rlx_init_streams(rlx_state *states, uint64_t n, const uint64_t *ids,
  * with that p); records of any other level are flagged RLX_ERR_BAD_P and
  * left unchanged, their outputs unwritten.  With more than
  * RLX_MAX_RECORD_LEVELS levels prepared on the device such a call returns
- * RLX_EINVAL.  A generate call then uses at most 64 lanes per record.  A
- * wave whose records share one level runs that level's step as a uniform
- * p call does; a wave that mixes levels multiplies lane by lane (several
- * times the vector work of a step: fully shuffled levels took 1.8 times the
- * one-level kernel's time on 65536 streams x 4096 doubles, level blocks
- * 1.1 times), so records sorted by level run fastest.
+ * RLX_EINVAL.  A generate call then uses at most 64 lanes per record.  The
+ * step runs on the matrix cores with one multiplier per half-wave, so a
+ * wave whose halves each hold records of one level (always the case with 32
+ * or 64 lanes per record) runs at about the one-level speed; a half-wave
+ * that mixes levels (fewer lanes per record, records not sorted by level)
+ * multiplies lane by lane, at several times the vector work of a step.
  * rlx_init_streams, rlx_generate_f64_trace, rlx_generate_f64_lcg52 and
  * rlx_import_ranlux take one level (RLX_P_RECORD -> RLX_EINVAL); batch plans
  * mix levels per request (rlx_plan_create). */

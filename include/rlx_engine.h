@@ -32,7 +32,17 @@
  * Calls may still be made under divergent control flow (each lane always
  * advances in time for itself); convergent calls are what make them cheap.
  *
- * Cost: about 40 VGPRs per engine (state, RANLUX numbers, position).
+ * Advance.  When the whole wave is active at an advance (the convergent
+ * case) the step runs on the int8 matrix cores for all 64 lanes at once
+ * (rlx_mfma.hpp, the library's step, with the operands of A_p from
+ * t.mfma); otherwise, or with t.mfma == NULL, on the vector ALU.  Both give
+ * the same state.
+ *
+ * Cost: about 40 VGPRs per engine (state, RANLUX numbers, position), plus
+ * the matrix-core step's 32 accumulators at an advance.  Give the kernel
+ * __attribute__((amdgpu_waves_per_eu(3))) (or a similar bound) so the
+ * compiler keeps those in ordinary registers instead of spilling to the
+ * accumulation registers.
  */
 #ifndef RLX_ENGINE_H
 #define RLX_ENGINE_H
@@ -43,6 +53,7 @@
 #include "rlx.h"
 #include "rlx_arith.hpp"
 #include "rlx_gauss.hpp"
+#include "rlx_mfma.hpp"
 
 /* One generator: the step t being drawn from and its position. */
 struct rlx_engine {
@@ -102,10 +113,25 @@ __device__ __forceinline__ void pow_windows16(uint32_t (&x)[rlx::NW], uint64_t k
 }
 
 /* The wave-synchronised lazy advance (see the header comment), then the
- * move to the next step once the current one is used up. */
+ * move to the next step once the current one is used up.  When every lane
+ * of the wave is active (the usual, convergent call) the step runs on the
+ * matrix cores for all 64 lanes (rlx_mfma.hpp, operands of A_p read through
+ * the L1) and the lanes that have not advanced yet take the result; under
+ * divergent control flow, or without matrix-core operands in the tables,
+ * the lanes that need it take the vector step.  Both give the same X. */
 __device__ __forceinline__ void before_draw(rlx_engine& e, const rlx_engine_tables& t) {
     if (__any(!e.ahead && e.pos == 11)) {
-        if (!e.ahead) {
+        if (t.mfma != nullptr && __builtin_amdgcn_read_exec() == ~0ull) {
+            uint32_t y[rlx::NW];
+#pragma unroll
+            for (int k = 0; k < rlx::NW; ++k) y[k] = e.x[k];
+            rlx::mfma_step(y, rlx::MfFromBuffer(t.mfma, __lane_id()), false);
+            if (!e.ahead) {
+#pragma unroll
+                for (int k = 0; k < rlx::NW; ++k) e.x[k] = y[k];
+                e.ahead = 1;
+            }
+        } else if (!e.ahead) {
             rlx::step(e.x, rlx::constant_table(t.folded), false, rlx::SgprBarrier());
             e.ahead = 1;
         }

@@ -160,8 +160,12 @@ struct MfFromBuffer {
   }
 };
 
-template <class Fetch>
-__device__ __forceinline__ void mfma_step(uint32_t (&x)[NW], const Fetch& fetch, bool force_general) {
+// The step with the A operands of fetch0 for the states of lanes 0..31
+// (state tile 0) and those of fetch1 for lanes 32..63 (tile 1): two
+// multipliers in one wave, one per half.
+template <class Fetch0, class Fetch1>
+__device__ __forceinline__ void mfma_step_halves(uint32_t (&x)[NW], const Fetch0& fetch0, const Fetch1& fetch1,
+                                                 bool force_general) {
   // signed input digits, halves exchanged across the two lane halves
   uint32_t a[9], b[9];
 #pragma unroll
@@ -182,13 +186,14 @@ __device__ __forceinline__ void mfma_step(uint32_t (&x)[NW], const Fetch& fetch,
   uint32_t h = 0;     // word 18
 #pragma unroll
   for (int mt = 0; mt < 3; ++mt) {
-    const mf_v4i f0 = fetch(3 * mt), f1 = fetch(3 * mt + 1), f2 = fetch(3 * mt + 2);
+    const mf_v4i f0 = fetch0(3 * mt), f1 = fetch0(3 * mt + 1), f2 = fetch0(3 * mt + 2);
+    const mf_v4i g0 = fetch1(3 * mt), g1 = fetch1(3 * mt + 1), g2 = fetch1(3 * mt + 2);
     mf_v16i s0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, b0[0], zero, 0, 0, 0);
-    mf_v16i s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f0, b1[0], zero, 0, 0, 0);
+    mf_v16i s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(g0, b1[0], zero, 0, 0, 0);
     s0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, b0[1], s0, 0, 0, 0);
-    s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f1, b1[1], s1, 0, 0, 0);
+    s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(g1, b1[1], s1, 0, 0, 0);
     s0 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, b0[2], s0, 0, 0, 0);
-    s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(f2, b1[2], s1, 0, 0, 0);
+    s1 = __builtin_amdgcn_mfma_i32_32x32x32_i8(g2, b1[2], s1, 0, 0, 0);
     // rows 64 + 8q + ... of the last tile are zero from q = 2 on (the
     // digits end at row 75)
     const int nq = mt < 2 ? 4 : 2;
@@ -233,6 +238,12 @@ __device__ __forceinline__ void mfma_step(uint32_t (&x)[NW], const Fetch& fetch,
     x[0] = w0; x[1] = w1; x[7] = w7; x[8] = w8; x[9] = w9;
     fold_word_general(x, h);
   }
+}
+
+// The step with one multiplier for the whole wave.
+template <class Fetch>
+__device__ __forceinline__ void mfma_step(uint32_t (&x)[NW], const Fetch& fetch, bool force_general) {
+  mfma_step_halves(x, fetch, fetch, force_general);
 }
 
 }  // namespace rlx

@@ -429,10 +429,12 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out:
 
 // k_generate for records of several levels (p = RLX_P_RECORD), G <= 64 lanes
 // per record, so a record's lanes share a wave and write it back in place.
-// A wave whose live records all have one level takes that level's
-// matrix-core step (operands read through the L1, as the batched kernel does
-// for items of mixed levels); a wave that mixes levels multiplies each lane
-// by its own level's A^G with the generic multiplication.
+// A wave in which each half (lanes 0..31, 32..63) has live records of one
+// level takes the matrix-core step with one multiplier per half (operands
+// read through the L1, as the batched kernel does for items of mixed
+// levels); with G >= 32 a half is one record, so this is every wave.  A wave
+// with mixed levels inside a half multiplies each lane by its own level's
+// A^G with the generic multiplication.
 template <Out K, int LGS>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out::NORMAL ? 3 : 4))) void k_generate_levels(
     rlx_state* __restrict__ st, uint32_t n, uint64_t count, uint64_t* __restrict__ out, LevelSet L, uint32_t lg,
@@ -462,11 +464,16 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out:
     pos = 0;
     li = -1;
   }
-  // the wave's level when all its live records share one
+  // each half-wave's level when its live records share one (the step takes
+  // one multiplier per half: lanes 0..31 and 32..63 are its two state
+  // tiles); a half with no live record takes the other half's
   const uint64_t act = __ballot(li >= 0);
-  const int first = act ? __ffsll((unsigned long long)act) - 1 : 0;
-  const int u = __builtin_amdgcn_readfirstlane(__shfl(li, first));
-  const bool uniform = __all(li < 0 || li == u);
+  const uint64_t act0 = act & 0xFFFFFFFFull, act1 = act >> 32;
+  const int first0 = act0 ? __ffsll((unsigned long long)act0) - 1 : (act1 ? 32 + __ffsll((unsigned long long)act1) - 1 : 0);
+  const int first1 = act1 ? 32 + __ffsll((unsigned long long)act1) - 1 : first0;
+  const int u0 = __builtin_amdgcn_readfirstlane(__shfl(li, first0));
+  const int u1 = __builtin_amdgcn_readfirstlane(__shfl(li, first1));
+  const bool uniform = __all(li < 0 || li == ((threadIdx.x & 32) ? u1 : u0));
   const uint32_t nadv = (uint32_t)((pos + count) / FIELDS);
   if (STAGED && active) skip_windows(x, l, level_ptr(L.W, li));
 
@@ -495,7 +502,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out:
     }
     if (__any(live && t + (1u << lg) <= nadv)) {
       if (uniform) {
-        mfma_step(x, MfFromBuffer(level_ptr(L.M, u) + (size_t)lg * MF_LEVEL_WORDS, threadIdx.x & 63), false);
+        mfma_step_halves(x, MfFromBuffer(level_ptr(L.M, u0) + (size_t)lg * MF_LEVEL_WORDS, threadIdx.x & 63),
+                         MfFromBuffer(level_ptr(L.M, u1) + (size_t)lg * MF_LEVEL_WORDS, threadIdx.x & 63), false);
       } else if (active) {
         uint32_t a[NW];
         load_words(level_ptr(L.C, li) + (size_t)lg * FOLD_ROW_WORDS, a);  // C_0 = A^G
