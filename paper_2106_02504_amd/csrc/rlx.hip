@@ -501,7 +501,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out:
       group_store<LGS>(stage, threadIdx.x, ls, jb, count, active, row);
     }
     if (__any(live && t + (1u << lg) <= nadv)) {
-      if (uniform) {
+      if (uniform && u0 == u1) {
+        // one level for the wave: one operand fetch serves both halves
+        mfma_step(x, MfFromBuffer(level_ptr(L.M, u0) + (size_t)lg * MF_LEVEL_WORDS, threadIdx.x & 63), false);
+      } else if (uniform) {
         mfma_step_halves(x, MfFromBuffer(level_ptr(L.M, u0) + (size_t)lg * MF_LEVEL_WORDS, threadIdx.x & 63),
                          MfFromBuffer(level_ptr(L.M, u1) + (size_t)lg * MF_LEVEL_WORDS, threadIdx.x & 63), false);
       } else if (active) {
