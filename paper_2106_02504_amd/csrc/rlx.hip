@@ -225,6 +225,31 @@ __global__ __launch_bounds__(BLOCK) void k_init(rlx_state* __restrict__ st, uint
   store_record(st, i, x, 0u, p);
 }
 
+// Record of the block that this thread skips when every record has its own
+// offset: the block's records ordered by the number of 16-bit windows of
+// their skip (a counting sort in LDS), so that each wave runs about as many
+// multiplication rounds as its own records need instead of the longest in
+// the block (offsets log-uniform over 64 bits: about 10 rounds per 4 waves
+// instead of 16).  Every thread of the block must call it; the order only
+// decides which lane handles which record.
+__device__ __forceinline__ uint64_t skip_record_index(const uint64_t* __restrict__ steps, uint64_t n,
+                                                      int by_values, uint32_t per_step) {
+  __shared__ uint32_t cnt[5];
+  __shared__ uint32_t order[BLOCK];
+  const uint64_t i = (uint64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const uint64_t k = i < n ? steps[i] / (by_values ? per_step : 1u) : 0;
+  const uint32_t key = k ? (uint32_t)(64 - __clzll((long long)k) + WIN_BITS - 1) / WIN_BITS : 0u;
+  if (threadIdx.x < 5) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t slot = atomicAdd(&cnt[key], 1u);
+  __syncthreads();
+  uint32_t base = 0;
+  for (uint32_t b = 0; b < key; ++b) base += cnt[b];
+  order[base + slot] = threadIdx.x;
+  __syncthreads();
+  return (uint64_t)blockIdx.x * BLOCK + order[threadIdx.x];
+}
+
 // by_values = 0: skip `steps` generator steps (pos unchanged); 1: skip that
 // many values of `per_step` values per step (pos + v = per_step k + pos',
 // k steps, new pos'): 12 for the 48-bit fields, 11 for the legacy 52-bit
@@ -233,7 +258,8 @@ __global__ __launch_bounds__(BLOCK) void k_skip(rlx_state* __restrict__ st, uint
                                                 const uint64_t* __restrict__ steps, uint64_t steps0,
                                                 uint32_t p, const uint32_t* __restrict__ W,
                                                 uint32_t* __restrict__ err, int by_values, uint32_t per_step) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i = steps ? skip_record_index(steps, n, by_values, per_step)
+                           : (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t x[NW], pos, sp;
   load_record(st, i, x, pos, sp);
@@ -290,7 +316,8 @@ __global__ __launch_bounds__(BLOCK) void k_skip_levels(rlx_state* __restrict__ s
                                                        const uint64_t* __restrict__ steps, uint64_t steps0,
                                                        LevelSet L, uint32_t* __restrict__ err, int by_values,
                                                        uint32_t per_step) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i = steps ? skip_record_index(steps, n, by_values, per_step)
+                           : (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   uint32_t x[NW], pos, sp;
   load_record(st, i, x, pos, sp);
