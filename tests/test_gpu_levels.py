@@ -57,6 +57,26 @@ def test_generate_f64_each_record_at_its_level(G, sort):
     assert rlx.check_errors() == 0
 
 
+@pytest.mark.parametrize("G", (16, 32, 64))
+def test_alternating_levels_per_half_wave(G):
+    # records alternate between two levels: at G = 32 each half-wave is one
+    # record, so every wave runs the step with a different multiplier per
+    # half; at G = 64 a wave is one record; at G = 16 a half-wave holds two
+    # records of different levels (the lane-by-lane path)
+    rlx.set_lanes_per_stream(G)
+    recs = [(O.seed(500 + i, (24, 2048)[i % 2]), (5 * i) % 12, (24, 2048)[i % 2]) for i in range(40)]
+    st = records_to_tensor(recs)
+    count = 1000
+    got = (rlx.generate_f64(st, count, rlx.P_RECORD) * 2.0 ** 48).to(torch.int64).cpu().numpy()
+    after = tensor_to_records(st)
+    for i in range(40):
+        x, pos, p = recs[i]
+        want, x2, pos2 = O.draws(x, pos, p, count)
+        assert got[i].tolist() == want, (G, i, p)
+        assert after[i] == (x2, pos2, p)
+    assert rlx.check_errors() == 0
+
+
 def test_uniform_waves_many_streams_shape():
     # 4096 streams in five level blocks of 819 (waves of one level at G = 32,
     # but for the one straddling each block boundary), 4096
