@@ -704,17 +704,29 @@ def main() -> int:
         del outu
     if "single" in wanted:
         st1 = rlx.new_states(1, device=dev)
+        out1 = torch.empty((1, 1 << 20), dtype=torch.float64, device=dev)
+        tr1 = torch.zeros((1, (11 + (1 << 20)) // 12 + 1, 9), dtype=torch.int64, device=dev)
+        ev1 = []
 
         def step_1():
             rlx.init_streams(st1, P, id0=1)
-            rlx.generate_f64_trace(st1, 1 << 20, P)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            rlx.generate_f64_trace(st1, 1 << 20, P, out=out1, trace=tr1)
+            e1.record(stream)
+            ev1.append((e0, e1))
         dt = timed(step_1, stream, 50, 10, torch)
+        torch.cuda.synchronize()
+        k1 = float(np.median([a.elapsed_time(b) for a, b in ev1[-50:]]))
+        ev1.clear()
         # the same stream in one lane: the latency of a generator step
         rlx.set_lanes_per_stream(1)
         dt1 = timed(step_1, stream, 1, 1, torch)
         rlx.set_lanes_per_stream(args.lanes)
         steps1 = (1 << 20) // 12 + 1
         legs["single"] = {"value": (1 << 20) / dt, "unit": "doubles/s", "ms_per_step": dt * 1e3,
+                          "kernel_ms": k1, "kernel_value": (1 << 20) / (k1 * 1e-3),
                           "lanes_per_stream": rlx.lanes_per_stream(1, 1 << 20),
                           "one_lane_ms": dt1 * 1e3, "one_lane_us_per_generator_step": dt1 * 1e6 / steps1,
                           "workload": "1 stream (id 1), p=2048, 2^20 doubles + state after each step"}

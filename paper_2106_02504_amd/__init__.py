@@ -349,13 +349,20 @@ def test_engine(states: torch.Tensor, count: int, p: int, mode: str) -> torch.Te
     return out
 
 
-def generate_f64_trace(states: torch.Tensor, count: int, p: int):
+def generate_f64_trace(states: torch.Tensor, count: int, p: int, out: torch.Tensor | None = None,
+                       trace: torch.Tensor | None = None):
     """generate_f64 plus the LCG state of every step visited:
-    returns (values [n, count], trace [n, steps, 9] int64)."""
+    returns (values [n, count], trace [n, steps, 9] int64), steps =
+    (11 + count) // 12 + 1; `out` and `trace` may be given (trace rows past
+    the last state visited are left as they are)."""
     n = _need_states(states)
     steps = (11 + count) // 12 + 1
-    out = _out(states, count, torch.float64, None)
-    trace = torch.zeros((n, steps, 9), dtype=torch.int64, device=states.device)
+    out = _out(states, count, torch.float64, out)
+    if trace is None:
+        trace = torch.zeros((n, steps, 9), dtype=torch.int64, device=states.device)
+    elif (trace.dtype != torch.int64 or tuple(trace.shape) != (n, steps, 9) or not trace.is_contiguous()
+          or trace.device != states.device):
+        raise ValueError(f"trace must be a contiguous int64 tensor of shape {(n, steps, 9)} on {states.device}")
     with torch.cuda.device(states.device):
         _check(lib().rlx_generate_f64_trace(states.data_ptr(), n, count, out.data_ptr(), trace.data_ptr(),
                                             steps, p, _stream()), "rlx_generate_f64_trace")
