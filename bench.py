@@ -726,7 +726,9 @@ def main() -> int:
         rlx.set_lanes_per_stream(args.lanes)
         steps1 = (1 << 20) // 12 + 1
         legs["single"] = {"value": (1 << 20) / dt, "unit": "doubles/s", "ms_per_step": dt * 1e3,
-                          "kernel_ms": k1, "kernel_value": (1 << 20) / (k1 * 1e-3),
+                          # the generate call alone (its kernel and, for a record that
+                          # spans several waves, the skip launch advancing it)
+                          "call_ms": k1, "call_value": (1 << 20) / (k1 * 1e-3),
                           "lanes_per_stream": rlx.lanes_per_stream(1, 1 << 20),
                           "one_lane_ms": dt1 * 1e3, "one_lane_us_per_generator_step": dt1 * 1e6 / steps1,
                           "workload": "1 stream (id 1), p=2048, 2^20 doubles + state after each step"}
