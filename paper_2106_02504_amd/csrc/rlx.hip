@@ -365,7 +365,7 @@ __global__ __launch_bounds__(BLOCK) void k_skip_levels(rlx_state* __restrict__ s
 // (writeback = 0) and the host advances it by a skip launch on the same
 // stream after this kernel.
 template <Out K, bool TRACE, int LGS, bool MF>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out::NORMAL ? 3 : 4))) void k_generate(rlx_state* __restrict__ st, uint32_t n,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out::NORMAL && LGS == 0 ? 3 : 4))) void k_generate(rlx_state* __restrict__ st, uint32_t n,
                                                     uint64_t count, uint64_t* __restrict__ out,
                                                     uint64_t* __restrict__ trace, uint64_t trace_steps,
                                                     const uint32_t* __restrict__ ctabs,
@@ -377,7 +377,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(K == Out:
   // index, lane, pos, last block): the host limits n < 2^32 and
   // count <= RLX_MAX_COUNT, so record and block indices fit in 32 bits.
   // Everything else is recomputed per iteration, which keeps the registers
-  // within 128 (4 waves per SIMD; 3 for normals) without spills.
+  // within 128 (4 waves per SIMD) without spills; normals without staging
+  // (one lane per record) need more and run 3 waves per SIMD.
   constexpr bool STAGED = LGS > 0;
   constexpr uint32_t gs = 1u << LGS;  // lanes of a record inside one wave
   __shared__ __align__(16) uint64_t stage[STAGED ? BLOCK * SLOT_VALUES : 2];
