@@ -218,8 +218,8 @@ __device__ __forceinline__ void write_values(const uint32_t (&lo)[NLO], const ui
     pair_values<K>(w0, w1, w2, a, b);
     s2[i] = make_ulonglong2(a, b);
     // normals: one pair's transform is finished before the next begins, so
-    // their temporaries never overlap (128 VGPRs, 4 waves per SIMD, instead
-    // of 166 and 3 when the scheduler interleaves all six)
+    // their temporaries never overlap (the staged generate kernel fits 128
+    // VGPRs and 4 waves per SIMD; interleaving all six took 166 and 3)
     if constexpr (K == Out::NORMAL) __builtin_amdgcn_sched_barrier(0);
   }
 }
